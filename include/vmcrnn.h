@@ -1,0 +1,153 @@
+/*
+ * vmcrnn.h -- C ABI of the MI355X (gfx950) variational-Monte-Carlo hot path
+ * for GRU recurrent-neural-network wave functions (McNaughton & Hibat-Allah,
+ * "Adaptive Neural Quantum States: A Recurrent Neural Network Perspective",
+ * arXiv 2507.18700).
+ *
+ * General conventions
+ *  - Every array argument is a DEVICE pointer owned by the caller, except the
+ *    descriptors (vmc_model, vmc_ham), which are host structs read during the
+ *    call.  No call allocates device memory: scratch space comes from the
+ *    caller's workspace `ws` of at least vmc_workspace_size() bytes, aligned
+ *    to 256 bytes.  The workspace holds no state between calls.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    All work is enqueued on it and the call returns without synchronising.
+ *    Calls on one workspace must not overlap (same stream or ordered).
+ *  - Argument errors are detected on the host before any launch and leave
+ *    every output untouched.  A launch failure returns VMC_EDEVICE.
+ *  - Spin configurations are uint8 in {0,1}, row-major [count][N], lattice
+ *    order: site (i,j) (column i < Lx, row j < Ly) at index j*Lx + i.
+ *    sigma = 0 is the +1 eigenvector of sigma^z.
+ *  - Parameters are float32, one flat vector per model, in this order
+ *    (row-major [out][in]; d = d_h):
+ *      1D GRU (App. A): W_g[d][d+2], b_g[d], W_r[d][d+2], b_r[d],
+ *                       W_h[d][d], b_h[d], W_in[d][2], b_in[d]
+ *                       (gate input order [h_{n-1}; onehot(sigma_{n-1})])
+ *      2D GRU (App. A): W[d][2d+4], b[d], W_g[d][2d+4], b_g[d], U[d][2d]
+ *                       (input order [h_hz; h_vt; onehot_hz; onehot_vt])
+ *      GLU (App. A, if glu):  W_1[d][d], b_1[d], W_2[d][d], b_2[d]
+ *      amplitude head (Eq. 3): U_a[2][d], c_a[2]
+ *      phase head (Eq. 5, if is_complex): U_p[2][d], c_p[2]
+ *  - Order of the autoregressive chain (Sec. II A): 1D runs over the sites;
+ *    2D runs in zig-zag order, even rows left to right, odd rows right to
+ *    left, with the predecessors (i-(-1)^j, j) and (i, j-1).  h_0 = 0 and a
+ *    missing neighbour contributes h = 0 and one-hot (0,0).
+ */
+#ifndef VMCRNN_H
+#define VMCRNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VMC_OK = 0,
+    VMC_EINVAL = -1,       /* bad argument (null pointer, size, descriptor) */
+    VMC_EUNSUPPORTED = -2, /* valid but not supported (e.g. d_h > 256) */
+    VMC_ENOSPACE = -3,     /* workspace smaller than vmc_workspace_size() */
+    VMC_EDEVICE = -4       /* a HIP call or kernel launch failed */
+} vmc_status;
+
+enum { VMC_FP32 = 0, VMC_BF16 = 1 };      /* GEMM operand precision */
+enum { VMC_TFIM = 0, VMC_HEISENBERG = 1 }; /* Hamiltonians, Eqs. (6), (7) */
+
+/* Wave-function descriptor.  N = Lx*Ly sites (1D: Ly = 1).  d_h in [1,256];
+ * d_model = d_h.  precision: VMC_FP32 = FP32 MFMA operands, VMC_BF16 =
+ * bfloat16 operands of the cell and GLU contractions (weights and hidden
+ * states rounded to nearest even), FP32 accumulation, FP32 activations and
+ * heads in both. */
+typedef struct {
+    int32_t dims;       /* 1 or 2 */
+    int32_t Lx, Ly;
+    int32_t d_h;
+    int32_t is_complex; /* complex RNN: softsign phase head (Eqs. 4-5) */
+    int32_t glu;        /* gated linear unit before the heads (App. A) */
+    int32_t precision;  /* VMC_FP32 or VMC_BF16 */
+} vmc_model;
+
+/* Hamiltonian with open boundaries on the chain (1D) or square lattice (2D):
+ *  VMC_TFIM       H = -J sum_<ab> Z_a Z_b - h sum_k X_k                (Eq. 6)
+ *  VMC_HEISENBERG H = J/4 sum_<ab> (X_a X_b + Y_a Y_b + Z_a Z_b)       (Eq. 7)
+ *                 with marshall != 0, the Marshall-sign rotated form whose
+ *                 off-diagonal elements are all negative (Sec. III B).     */
+typedef struct {
+    int32_t kind;
+    int32_t marshall;
+    double J, h;
+} vmc_ham;
+
+/* Number of float parameters of the flat vector described above; -1 if the
+ * descriptor is invalid. */
+int64_t vmc_param_count(const vmc_model *m);
+
+/* Workspace bytes needed by any call below with this model, Hamiltonian
+ * (may be NULL when local_energy is not used) and up to `ns` samples or
+ * configurations per call. */
+vmc_status vmc_workspace_size(const vmc_model *m, const vmc_ham *H, int64_t ns, size_t *bytes);
+
+/* Perfect autoregressive sampling (Sec. II A, Eq. 1): for each sample s and
+ * order position n, sigma_n = 0 if u[s][n] < P(sigma_n = 0 | sigma_<n), else 1.
+ *  uniforms: [ns][N] float in [0,1), indexed by ORDER position; or NULL, in
+ *            which case u[s][n] = (word n%4 of Philox4x32-10(key = seed,
+ *            ctr = {n/4, s, counter_lo, counter_hi}) >> 8) * 2^-24
+ *            (Salmon et al., SC'11).  ns must be < 2^32.
+ *  configs:  out [ns][N] uint8, lattice order.
+ *  logp:     out [ns] log P(sigma) (log |psi|^2, Eq. 3 chained by Eq. 1).
+ *  phase:    out [ns] phi(sigma) (Eq. 5), or NULL; ignored for positive RNNs. */
+vmc_status rnn_sample(const vmc_model *m, const float *params, int64_t ns, uint64_t seed,
+                      uint64_t counter, const float *uniforms, uint8_t *configs, float *logp,
+                      float *phase, void *ws, size_t ws_bytes, void *stream);
+
+/* Teacher-forced log P and phase of nc given configurations (Eqs. 1, 3, 5);
+ * log psi = logp/2 + i*phase (Eq. 4).  phase may be NULL. */
+vmc_status rnn_logpsi(const vmc_model *m, const float *params, int64_t nc,
+                      const uint8_t *configs, float *logp, float *phase, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* Local energy E_loc(sigma) = sum_sigma' H(sigma,sigma') psi(sigma')/psi(sigma)
+ * for ns configurations (Eqs. 6, 7).  Every connected configuration of every
+ * sample is evaluated in the same call; only the part of the chain after the
+ * first changed order position is recomputed.
+ *  eloc: out [ns][2] double (real, imaginary). */
+vmc_status local_energy(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns,
+                        const uint8_t *configs, double *eloc, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* Energy statistics and the covariance estimate of the energy gradient
+ * (VMC with the normalised autoregressive ansatz, Sec. III):
+ *    Ebar = sum_s w_s E_s,  var = sum_s w_s |E_s - Ebar|^2,
+ *    grad = 2 Re sum_s w_s conj(E_s - Ebar) d log psi(sigma_s)
+ *         = sum_s w_s [Re(E_s-Ebar) d logP_s + 2 Im(E_s-Ebar) d phi_s],
+ * with E held constant.  weights: [ns] double or NULL (w_s = 1/ns).
+ *  eloc:  [ns][2] double.   grad: out [vmc_param_count] double.
+ *  stats: out [4] double: Re Ebar, Im Ebar, var, count of non-finite E_s.
+ * Cross-sample sums are FP64 in a fixed order (bitwise reproducible). */
+vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const uint8_t *configs,
+                    const double *eloc, const double *weights, double *grad, double *stats,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* Adaptive growth of the hidden width (Sec. II B, Fig. 2(b); App. B):
+ * copies every parameter of `from` into the model with d_h = new_dh
+ * (new hidden units at the end of each h-block of every matrix, one-hot
+ * columns keep their order), fills every new entry with noise_std * z,
+ * z standard normal from Box-Muller on Philox4x32-10(key = seed,
+ * ctr = {e_lo, e_hi, 0, 0}) at destination index e (u1 = (w0>>8 + 1)/2^24,
+ * u2 = (w1>>8)/2^24), and pads the Adam moments with zeros.
+ *  p_from: [vmc_param_count(from)]; p_to: [count at new_dh].
+ *  m_from/v_from/m_to/v_to: moments, all four NULL or all four non-NULL.
+ *  new_dh must be >= from->d_h. */
+vmc_status grow_hidden(const vmc_model *from, const float *p_from, int32_t new_dh, uint64_t seed,
+                       double noise_std, float *p_to, const float *m_from, const float *v_from,
+                       float *m_to, float *v_to, void *stream);
+
+/* Static description of a status code. */
+const char *vmc_status_str(vmc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VMCRNN_H */

@@ -1,0 +1,349 @@
+// Host side of the C ABI declared in include/vmcrnn.h: argument checks,
+// workspace layout and the launch sequence of each call.
+#include <string.h>
+
+#include "kernels.h"
+
+namespace vmc {
+
+hipError_t launch_stage(const Dims &d, const float *prm, void *Bc, void *BcT, void *Bg, void *BgT,
+                        float *E, float *Hd, float *hc, hipStream_t st);
+hipError_t launch_forward(const FwdArgs &a, int mode, int store_h, int store_lpc, int store_act,
+                          int grid, hipStream_t st);
+hipError_t launch_sched(int ham_kind, int Lx, int Ly, int64_t ns, const uint8_t *cfg, int *cnt,
+                        int *list_off, int *list, int *tile_start, int *tile_counter, int MT,
+                        hipStream_t st);
+hipError_t launch_assemble(const vmc_ham &H, int Lx, int Ly, int64_t ns, const uint8_t *cfg,
+                           const float *lpc, const float *phc, const float2 *dsuf, int NC, double *eloc,
+                           hipStream_t st);
+int forward_tile_rows(int DH);
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
+hipError_t launch_grad(const Dims &d, const void *BcT, const void *BgT, const float *E, const float *Hd,
+                       int64_t ns, const uint8_t *cfg, const float *hcache, const float *act,
+                       const double *eloc, const double *weights, double *stats, float *dcell,
+                       float *dglu, float *dhead, void *dcol, float *part, int G, double *grad_st,
+                       double *grad, hipStream_t st);
+void grad_sizes(const Dims &d, int64_t ns, int *G, size_t *part_floats, size_t *gst_doubles);
+hipError_t launch_grow(const vmc_model &from, const float *p0, int new_dh, uint64_t seed, double noise,
+                       float *p1, const float *m0, const float *v0, float *m1, float *v1,
+                       int64_t n_to, hipStream_t st);
+
+static const int kMaxN = 1024;
+
+static bool valid_model(const vmc_model *m) {
+    if (!m) return false;
+    if (m->dims != 1 && m->dims != 2) return false;
+    if (m->Lx < 1 || m->Ly < 1 || (m->dims == 1 && m->Ly != 1)) return false;
+    if ((int64_t)m->Lx * m->Ly < 2 || (int64_t)m->Lx * m->Ly > kMaxN) return false;
+    if (m->d_h < 1) return false;
+    if (m->precision != VMC_FP32 && m->precision != VMC_BF16) return false;
+    if ((m->is_complex != 0 && m->is_complex != 1) || (m->glu != 0 && m->glu != 1)) return false;
+    return true;
+}
+
+static int padded_dh(int d) {
+    static const int sizes[] = {16, 32, 64, 128, 256};
+    for (int s : sizes)
+        if (d <= s) return s;
+    return -1;
+}
+
+static Dims make_dims(const vmc_model *m) {
+    Dims d;
+    d.dims = m->dims;
+    d.Lx = m->Lx;
+    d.Ly = m->dims == 2 ? m->Ly : 1;
+    d.N = d.Lx * d.Ly;
+    d.dh = m->d_h;
+    d.DH = padded_dh(m->d_h);
+    d.K = d.dims == 1 ? d.DH : 2 * d.DH;
+    int ks = m->precision == VMC_BF16 ? 32 : 16;
+    d.KP = round_up(d.K, ks);
+    d.cplx = m->is_complex;
+    d.glu = m->glu;
+    d.prec = m->precision;
+    return d;
+}
+
+static int device_cus() {
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            cached = n;
+        else
+            cached = 256;
+    }
+    return cached;
+}
+
+static size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+// Workspace map; offsets in bytes from the workspace base.
+struct WsMap {
+    size_t Bc, BcT, Bg, BgT, E, Hd, hc;
+    size_t hcache, lpc, phc, dsuf;
+    size_t cnt, list_off, tile_start, tile_counter, list;
+    size_t colbuf;
+    size_t act, dcell, dglu, dhead, dcol, part, gst, stats;
+    size_t total;
+    int chain_grid, fwd_grid, NC, G;
+};
+
+static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
+    WsMap w;
+    memset(&w, 0, sizeof(w));
+    const size_t es = d.prec == VMC_BF16 ? 2 : 4;
+    const int KGP = round_up(d.DH, d.prec == VMC_BF16 ? 32 : 16);
+    const int MT = forward_tile_rows(d.DH);
+    size_t o = 0;
+    auto put = [&](size_t bytes) {
+        size_t at = o;
+        o += al(bytes);
+        return at;
+    };
+    w.Bc = put((size_t)3 * d.DH * d.KP * es);
+    w.BcT = put((size_t)3 * d.DH * d.KP * es);
+    w.Bg = put((size_t)2 * d.DH * KGP * es);
+    w.BgT = put((size_t)2 * d.DH * KGP * es);
+    w.E = put((size_t)ESLOTS * d.DH * 4);
+    w.Hd = put((size_t)4 * d.DH * 4);
+    w.hc = put(16);
+    w.hcache = put((size_t)d.N * ns * d.DH * 4);
+    w.lpc = put((size_t)ns * d.N * 2 * 4);
+    w.phc = put((size_t)ns * d.N * 2 * 4);
+    const int nb = bond_count(d.Lx, d.Ly);
+    w.NC = (H && H->kind == VMC_HEISENBERG) ? nb : d.N;
+    w.dsuf = put((size_t)ns * w.NC * 8);
+    w.cnt = put((size_t)(d.N + 1) * 4);
+    w.list_off = put((size_t)(d.N + 1) * 4);
+    w.tile_start = put((size_t)(d.N + 1) * 4);
+    w.tile_counter = put(4);
+    w.list = put((H && H->kind == VMC_HEISENBERG) ? (size_t)ns * nb * 4 : 4);
+    w.fwd_grid = (int)((ns + MT - 1) / MT);
+    w.chain_grid = 2 * device_cus();
+    const int g = w.fwd_grid > w.chain_grid ? w.fwd_grid : w.chain_grid;
+    w.colbuf = put(d.dims == 2 ? (size_t)g * d.Lx * MT * d.DH * es : 16);
+    // backward
+    const int NA = nact_per_unit(d.dims);
+    const size_t AW = (size_t)(NA + 3) * d.DH + 4;
+    w.act = put((size_t)d.N * ns * AW * 4);
+    const int nd_cell = d.dims == 1 ? 4 * d.DH : 3 * d.DH;
+    w.dcell = put((size_t)d.N * ns * nd_cell * 4);
+    w.dglu = put(d.glu ? (size_t)d.N * ns * 2 * d.DH * 4 : 16);
+    w.dhead = put((size_t)d.N * ns * 4 * 4);
+    w.dcol = put(d.dims == 2 ? (size_t)w.fwd_grid * d.Lx * MT * d.DH * 4 : 16);
+    size_t part_floats = 0, gst_doubles = 0;
+    grad_sizes(d, ns, &w.G, &part_floats, &gst_doubles);
+    w.part = put(part_floats * 4);
+    w.gst = put(gst_doubles * 8);
+    w.stats = put(8 * 8);
+    w.total = o;
+    return w;
+}
+
+template <class X>
+static X *at(void *ws, size_t off) {
+    return (X *)((char *)ws + off);
+}
+
+static vmc_status hip_status(hipError_t e) { return e == hipSuccess ? VMC_OK : VMC_EDEVICE; }
+
+static vmc_status check_common(const vmc_model *m, const float *params, int64_t n, void *ws, size_t ws_bytes,
+                               const vmc_ham *H, size_t *need) {
+    if (!valid_model(m) || !params || n < 1 || !ws) return VMC_EINVAL;
+    if (((uintptr_t)ws & 255) != 0) return VMC_EINVAL;
+    if (padded_dh(m->d_h) < 0) return VMC_EUNSUPPORTED;
+    if (n >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
+    Dims d = make_dims(m);
+    if ((int64_t)forward_tile_rows(d.DH) * d.N > 32768) return VMC_EUNSUPPORTED;
+    if (H && H->kind == VMC_HEISENBERG && n * bond_count(d.Lx, d.Ly) >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
+    WsMap w = ws_map(d, H, n);
+    if (need) *need = w.total;
+    if (ws_bytes < w.total) return VMC_ENOSPACE;
+    return VMC_OK;
+}
+
+static hipError_t stage(const Dims &d, const float *params, void *ws, const WsMap &w, hipStream_t st) {
+    return launch_stage(d, params, at<void>(ws, w.Bc), at<void>(ws, w.BcT), at<void>(ws, w.Bg),
+                        at<void>(ws, w.BgT), at<float>(ws, w.E), at<float>(ws, w.Hd), at<float>(ws, w.hc), st);
+}
+
+static FwdArgs base_args(const Dims &d, void *ws, const WsMap &w, int64_t ns) {
+    FwdArgs a;
+    memset(&a, 0, sizeof(a));
+    a.d = d;
+    a.Bc = at<void>(ws, w.Bc);
+    a.Bg = at<void>(ws, w.Bg);
+    a.E = at<float>(ws, w.E);
+    a.Hd = at<float>(ws, w.Hd);
+    a.hc = at<float>(ws, w.hc);
+    a.nrows = ns;
+    a.ns_cache = ns;
+    a.colbuf = at<void>(ws, w.colbuf);
+    return a;
+}
+
+}  // namespace vmc
+
+using namespace vmc;
+
+extern "C" {
+
+int64_t vmc_param_count(const vmc_model *m) {
+    if (!valid_model(m)) return -1;
+    return param_layout(m->dims, m->d_h, m->glu, m->is_complex).total;
+}
+
+vmc_status vmc_workspace_size(const vmc_model *m, const vmc_ham *H, int64_t ns, size_t *bytes) {
+    if (!valid_model(m) || ns < 1 || !bytes) return VMC_EINVAL;
+    if (padded_dh(m->d_h) < 0) return VMC_EUNSUPPORTED;
+    if (H && H->kind != VMC_TFIM && H->kind != VMC_HEISENBERG) return VMC_EINVAL;
+    Dims d = make_dims(m);
+    *bytes = ws_map(d, H, ns).total;
+    return VMC_OK;
+}
+
+vmc_status rnn_sample(const vmc_model *m, const float *params, int64_t ns, uint64_t seed, uint64_t counter,
+                      const float *uniforms, uint8_t *configs, float *logp, float *phase, void *ws,
+                      size_t ws_bytes, void *stream) {
+    vmc_status s = check_common(m, params, ns, ws, ws_bytes, NULL, NULL);
+    if (s != VMC_OK) return s;
+    if (!configs || !logp) return VMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Dims d = make_dims(m);
+    WsMap w = ws_map(d, NULL, ns);
+    hipError_t e = stage(d, params, ws, w, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    FwdArgs a = base_args(d, ws, w, ns);
+    a.uniforms = uniforms;
+    a.seed = seed;
+    a.counter = counter;
+    a.cfg_out = configs;
+    a.logp = logp;
+    a.phase = d.cplx ? phase : NULL;
+    if (phase && !d.cplx) {
+        e = launch_fill(phase, ns, 0.0f, st);
+        if (e != hipSuccess) return VMC_EDEVICE;
+    }
+    return hip_status(launch_forward(a, MODE_SAMPLE, 0, 0, 0, w.fwd_grid, st));
+}
+
+vmc_status rnn_logpsi(const vmc_model *m, const float *params, int64_t nc, const uint8_t *configs, float *logp,
+                      float *phase, void *ws, size_t ws_bytes, void *stream) {
+    vmc_status s = check_common(m, params, nc, ws, ws_bytes, NULL, NULL);
+    if (s != VMC_OK) return s;
+    if (!configs || !logp) return VMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Dims d = make_dims(m);
+    WsMap w = ws_map(d, NULL, nc);
+    hipError_t e = stage(d, params, ws, w, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    FwdArgs a = base_args(d, ws, w, nc);
+    a.cfg_in = configs;
+    a.logp = logp;
+    a.phase = d.cplx ? phase : NULL;
+    if (phase && !d.cplx) {
+        e = launch_fill(phase, nc, 0.0f, st);
+        if (e != hipSuccess) return VMC_EDEVICE;
+    }
+    return hip_status(launch_forward(a, MODE_LOGPSI, 0, 0, 0, w.fwd_grid, st));
+}
+
+vmc_status local_energy(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns,
+                        const uint8_t *configs, double *eloc, void *ws, size_t ws_bytes, void *stream) {
+    if (!H || (H->kind != VMC_TFIM && H->kind != VMC_HEISENBERG)) return VMC_EINVAL;
+    vmc_status s = check_common(m, params, ns, ws, ws_bytes, H, NULL);
+    if (s != VMC_OK) return s;
+    if (!configs || !eloc) return VMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Dims d = make_dims(m);
+    WsMap w = ws_map(d, H, ns);
+    const int MT = forward_tile_rows(d.DH);
+    hipError_t e = stage(d, params, ws, w, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    // 1. teacher-forced pass: prefix hidden states and conditionals of every sample
+    FwdArgs a = base_args(d, ws, w, ns);
+    a.cfg_in = configs;
+    a.hcache = at<float>(ws, w.hcache);
+    a.lpc = at<float>(ws, w.lpc);
+    a.phc = at<float>(ws, w.phc);
+    e = launch_forward(a, MODE_LOGPSI, 1, 1, 0, w.fwd_grid, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    // 2. connection list and tile schedule
+    e = launch_sched(H->kind, d.Lx, d.Ly, ns, configs, at<int>(ws, w.cnt), at<int>(ws, w.list_off),
+                     at<int>(ws, w.list), at<int>(ws, w.tile_start), at<int>(ws, w.tile_counter), MT, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    // 3. all suffix chains of all samples in one persistent launch
+    a.ham_kind = H->kind;
+    a.nbond = bond_count(d.Lx, d.Ly);
+    a.cnt = at<int>(ws, w.cnt);
+    a.tile_start = at<int>(ws, w.tile_start);
+    a.list_off = at<int>(ws, w.list_off);
+    a.list = at<int>(ws, w.list);
+    a.tile_counter = at<int>(ws, w.tile_counter);
+    a.dsuf = at<float2>(ws, w.dsuf);
+    a.NC = w.NC;
+    a.logp = NULL;
+    a.phase = NULL;
+    e = launch_forward(a, MODE_CHAIN, 0, 0, 0, w.chain_grid, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    // 4. assembly
+    return hip_status(launch_assemble(*H, d.Lx, d.Ly, ns, configs, at<float>(ws, w.lpc), at<float>(ws, w.phc),
+                                      at<float2>(ws, w.dsuf), w.NC, eloc, st));
+}
+
+vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const uint8_t *configs,
+                    const double *eloc, const double *weights, double *grad, double *stats, void *ws,
+                    size_t ws_bytes, void *stream) {
+    vmc_status s = check_common(m, params, ns, ws, ws_bytes, NULL, NULL);
+    if (s != VMC_OK) return s;
+    if (!configs || !eloc || !grad) return VMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Dims d = make_dims(m);
+    WsMap w = ws_map(d, NULL, ns);
+    hipError_t e = stage(d, params, ws, w, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    FwdArgs a = base_args(d, ws, w, ns);
+    a.cfg_in = configs;
+    a.hcache = at<float>(ws, w.hcache);
+    a.act = at<float>(ws, w.act);
+    e = launch_forward(a, MODE_LOGPSI, 1, 0, 1, w.fwd_grid, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    double *st_out = stats ? stats : at<double>(ws, w.stats);
+    return hip_status(launch_grad(d, at<void>(ws, w.BcT), at<void>(ws, w.BgT), at<float>(ws, w.E),
+                                  at<float>(ws, w.Hd), ns, configs, at<float>(ws, w.hcache), at<float>(ws, w.act),
+                                  eloc, weights, st_out, at<float>(ws, w.dcell), at<float>(ws, w.dglu),
+                                  at<float>(ws, w.dhead), at<void>(ws, w.dcol), at<float>(ws, w.part), w.G,
+                                  at<double>(ws, w.gst), grad, st));
+}
+
+vmc_status grow_hidden(const vmc_model *from, const float *p_from, int32_t new_dh, uint64_t seed, double noise_std,
+                       float *p_to, const float *m_from, const float *v_from, float *m_to, float *v_to,
+                       void *stream) {
+    if (!valid_model(from) || !p_from || !p_to) return VMC_EINVAL;
+    if (new_dh < from->d_h) return VMC_EINVAL;
+    if (!(noise_std >= 0.0)) return VMC_EINVAL;
+    int nmom = (m_from != NULL) + (v_from != NULL) + (m_to != NULL) + (v_to != NULL);
+    if (nmom != 0 && nmom != 4) return VMC_EINVAL;
+    vmc_model to = *from;
+    to.d_h = new_dh;
+    if (!valid_model(&to)) return VMC_EINVAL;
+    int64_t n_to = param_layout(to.dims, new_dh, to.glu, to.is_complex).total;
+    return hip_status(launch_grow(*from, p_from, new_dh, seed, noise_std, p_to, m_from, v_from, m_to, v_to, n_to,
+                                  (hipStream_t)stream));
+}
+
+const char *vmc_status_str(vmc_status s) {
+    switch (s) {
+        case VMC_OK: return "ok";
+        case VMC_EINVAL: return "invalid argument";
+        case VMC_EUNSUPPORTED: return "unsupported configuration";
+        case VMC_ENOSPACE: return "workspace too small";
+        case VMC_EDEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// Kernel-side declarations shared by the library's translation units.
+#pragma once
+#include "common.h"
+
+namespace vmc {
+
+// Everything a forward-engine launch needs (passed by value).
+struct FwdArgs {
+    Dims d;
+    // staged weights (store_t arrays are passed as void*)
+    const void *Bc, *Bg;
+    const float *E, *Hd, *hc;
+    // inputs
+    int64_t nrows;           // samples (SAMPLE/LOGPSI)
+    const uint8_t *cfg_in;   // [ns][N] lattice order (LOGPSI, CHAIN)
+    const float *uniforms;   // [ns][N] order-indexed or NULL (SAMPLE)
+    uint64_t seed, counter;  // Philox (SAMPLE without uniforms)
+    // outputs
+    uint8_t *cfg_out;        // SAMPLE
+    float *logp, *phase;     // SAMPLE/LOGPSI, may be NULL
+    // caches (NULL = not written / not read)
+    float *hcache;           // [N][ns][DH] fp32 hidden states
+    float *lpc, *phc;        // [ns][N][2] log-conditionals, phase conditionals
+    float *act;              // [N][ns][NACT*DH] activations for the backward
+    float *ain;              // [N][ns][KA] augmented cell inputs for the backward
+    int64_t ns_cache;        // row count of the cache arrays
+    // per-workgroup scratch: column buffer of the 2D chain [grid][Lx][MT][DH]
+    void *colbuf;
+    // CHAIN mode
+    int ham_kind;            // 0 TFIM, 1 Heisenberg
+    int nbond;
+    const int *cnt, *tile_start, *list_off, *list;
+    int *tile_counter;
+    float2 *dsuf;            // [ns][NC] suffix sums (dlogP, dphi)
+    int NC;
+};
+
+enum { MODE_SAMPLE = 0, MODE_LOGPSI = 1, MODE_CHAIN = 2 };
+
+// number of activation floats per (position, sample) row stored for the backward
+__host__ __device__ inline int nact_per_unit(int dims) { return dims == 1 ? 4 : 3; }
+// augmented cell-input width: [h_hz | h_vt] (K) + 1 + one-hots (2 or 4)
+__host__ __device__ inline int ain_width(int dims, int DH) {
+    return dims == 1 ? round_up(DH + 3, 16) : round_up(2 * DH + 5, 16);
+}
+
+// bonds of the open chain / square lattice in the order used everywhere:
+// for each site a = j*Lx+i in lattice order, the bond to (i+1,j) then (i,j+1)
+__host__ __device__ inline int bond_count(int Lx, int Ly) { return (Lx - 1) * Ly + Lx * (Ly - 1); }
+__host__ __device__ inline void bond_sites(int b, int Lx, int Ly, int &a, int &c) {
+    int per = 2 * Lx - 1;
+    int j = b / per;
+    if (j < Ly - 1) {
+        int r = b - j * per;
+        if (r == 2 * Lx - 2) {
+            a = j * Lx + Lx - 1;
+            c = a + Lx;
+        } else {
+            int i = r >> 1;
+            a = j * Lx + i;
+            c = (r & 1) ? a + Lx : a + 1;
+        }
+    } else {
+        int i = b - (Ly - 1) * per;
+        a = (Ly - 1) * Lx + i;
+        c = a + 1;
+    }
+}
+
+}  // namespace vmc

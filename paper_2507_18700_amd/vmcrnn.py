@@ -1,0 +1,222 @@
+"""Python binding of libvmcrnn.so (the C ABI of include/vmcrnn.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch provides device memory (outputs and the workspace) and
+the current HIP stream.  The functions have the names of the C entry points.
+If the library is not built, every call raises; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvmcrnn.so")
+
+VMC_FP32, VMC_BF16 = 0, 1
+VMC_TFIM, VMC_HEISENBERG = 0, 1
+
+EXPORTS = ("vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "local_energy",
+           "vmc_grad", "grow_hidden", "vmc_status_str")
+
+
+class VmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (status %d)" % (msg, status))
+        self.status = status
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32), ("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32),
+                ("d_h", ctypes.c_int32), ("is_complex", ctypes.c_int32), ("glu", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+    @property
+    def N(self):
+        return self.Lx * self.Ly
+
+
+class Ham(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("marshall", ctypes.c_int32), ("J", ctypes.c_double),
+                ("h", ctypes.c_double)]
+
+
+def model(dims=1, Lx=4, Ly=1, d_h=16, is_complex=False, glu=False, precision=VMC_FP32):
+    return Model(dims, Lx, Ly if dims == 2 else 1, d_h, int(is_complex), int(glu), int(precision))
+
+
+def ham(kind=VMC_TFIM, J=1.0, h=1.0, marshall=False):
+    return Ham(kind, int(marshall), float(J), float(h))
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libvmcrnn.so is not built (run __graft_entry__.build()); "
+                               "there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp, i64, u64, sz, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double
+        L.vmc_param_count.restype = i64
+        L.vmc_param_count.argtypes = [P(Model)]
+        L.vmc_workspace_size.restype = ctypes.c_int
+        L.vmc_workspace_size.argtypes = [P(Model), P(Ham), i64, P(sz)]
+        L.rnn_sample.restype = ctypes.c_int
+        L.rnn_sample.argtypes = [P(Model), vp, i64, u64, u64, vp, vp, vp, vp, vp, sz, vp]
+        L.rnn_logpsi.restype = ctypes.c_int
+        L.rnn_logpsi.argtypes = [P(Model), vp, i64, vp, vp, vp, vp, sz, vp]
+        L.local_energy.restype = ctypes.c_int
+        L.local_energy.argtypes = [P(Model), vp, P(Ham), i64, vp, vp, vp, sz, vp]
+        L.vmc_grad.restype = ctypes.c_int
+        L.vmc_grad.argtypes = [P(Model), vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.grow_hidden.restype = ctypes.c_int
+        L.grow_hidden.argtypes = [P(Model), vp, ctypes.c_int32, u64, d, vp, vp, vp, vp, vp, vp]
+        L.vmc_status_str.restype = ctypes.c_char_p
+        L.vmc_status_str.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise VmcError(status, lib().vmc_status_str(status).decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError("%s must be a contiguous %s tensor on the GPU" % (name, dtype))
+    return t
+
+
+def param_count(m):
+    n = lib().vmc_param_count(ctypes.byref(m))
+    if n < 0:
+        raise VmcError(-1, "invalid model descriptor")
+    return n
+
+
+def workspace_size(m, H, ns):
+    out = ctypes.c_size_t(0)
+    _check(lib().vmc_workspace_size(ctypes.byref(m), None if H is None else ctypes.byref(H), ns,
+                                    ctypes.byref(out)))
+    return out.value
+
+
+class Workspace:
+    """Caller-owned device scratch passed to every call (grows on demand)."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes):
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws = {}
+
+
+def _ws(ws, m, H, ns):
+    need = workspace_size(m, H, ns)
+    if ws is None:
+        dev = torch.cuda.current_device()
+        ws = _default_ws.setdefault(dev, Workspace("cuda:%d" % dev))
+    buf = ws.get(need)
+    return buf, buf.numel()
+
+
+def rnn_sample(m, params, ns, seed=0, counter=0, uniforms=None, ws=None, out=None):
+    """Autoregressive sampling; returns (configs uint8 [ns,N], logp [ns], phase [ns])."""
+    _dev(params, torch.float32, "params")
+    dev = params.device
+    if uniforms is not None:
+        _dev(uniforms, torch.float32, "uniforms")
+        if uniforms.shape != (ns, m.N):
+            raise ValueError("uniforms must have shape [ns, N]")
+    if out is None:
+        out = (torch.empty((ns, m.N), dtype=torch.uint8, device=dev),
+               torch.empty(ns, dtype=torch.float32, device=dev),
+               torch.empty(ns, dtype=torch.float32, device=dev))
+    cfg, lp, ph = out
+    buf, nb = _ws(ws, m, None, ns)
+    _check(lib().rnn_sample(ctypes.byref(m), _ptr(params), ns, seed, counter, _ptr(uniforms), _ptr(cfg),
+                            _ptr(lp), _ptr(ph), _ptr(buf), nb, _stream()))
+    return cfg, lp, ph
+
+
+def rnn_logpsi(m, params, configs, ws=None):
+    """Teacher-forced (logp [nc], phase [nc]) of given configurations."""
+    _dev(params, torch.float32, "params")
+    _dev(configs, torch.uint8, "configs")
+    nc = configs.shape[0]
+    lp = torch.empty(nc, dtype=torch.float32, device=params.device)
+    ph = torch.empty(nc, dtype=torch.float32, device=params.device)
+    buf, nb = _ws(ws, m, None, nc)
+    _check(lib().rnn_logpsi(ctypes.byref(m), _ptr(params), nc, _ptr(configs), _ptr(lp), _ptr(ph), _ptr(buf),
+                            nb, _stream()))
+    return lp, ph
+
+
+def local_energy(m, params, H, configs, ws=None, out=None):
+    """Local energies [ns, 2] float64 (real, imaginary)."""
+    _dev(params, torch.float32, "params")
+    _dev(configs, torch.uint8, "configs")
+    ns = configs.shape[0]
+    e = out if out is not None else torch.empty((ns, 2), dtype=torch.float64, device=params.device)
+    buf, nb = _ws(ws, m, H, ns)
+    _check(lib().local_energy(ctypes.byref(m), _ptr(params), ctypes.byref(H), ns, _ptr(configs), _ptr(e),
+                              _ptr(buf), nb, _stream()))
+    return e
+
+
+def vmc_grad(m, params, configs, eloc, weights=None, ws=None, out=None):
+    """Covariance energy gradient; returns (grad float64 [P], stats float64 [4])."""
+    _dev(params, torch.float32, "params")
+    _dev(configs, torch.uint8, "configs")
+    _dev(eloc, torch.float64, "eloc")
+    if weights is not None:
+        _dev(weights, torch.float64, "weights")
+    ns = configs.shape[0]
+    if out is None:
+        out = (torch.empty(param_count(m), dtype=torch.float64, device=params.device),
+               torch.empty(4, dtype=torch.float64, device=params.device))
+    g, st = out
+    buf, nb = _ws(ws, m, None, ns)
+    _check(lib().vmc_grad(ctypes.byref(m), _ptr(params), ns, _ptr(configs), _ptr(eloc), _ptr(weights), _ptr(g),
+                          _ptr(st), _ptr(buf), nb, _stream()))
+    return g, st
+
+
+def grow_hidden(m, params, new_dh, seed, noise_std, m_mom=None, v_mom=None):
+    """Grown parameters (and moments if given) at hidden width new_dh."""
+    _dev(params, torch.float32, "params")
+    to = Model(m.dims, m.Lx, m.Ly, new_dh, m.is_complex, m.glu, m.precision)
+    n1 = param_count(to)
+    p1 = torch.empty(n1, dtype=torch.float32, device=params.device)
+    mm = vv = None
+    if m_mom is not None or v_mom is not None:
+        _dev(m_mom, torch.float32, "m")
+        _dev(v_mom, torch.float32, "v")
+        mm = torch.empty_like(p1)
+        vv = torch.empty_like(p1)
+    _check(lib().grow_hidden(ctypes.byref(m), _ptr(params), new_dh, seed, float(noise_std), _ptr(p1),
+                             _ptr(m_mom), _ptr(v_mom), _ptr(mm), _ptr(vv), _stream()))
+    if mm is not None:
+        return p1, mm, vv, to
+    return p1, to
