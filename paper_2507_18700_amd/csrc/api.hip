@@ -104,7 +104,7 @@ static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
         return at;
     };
     w.Bc = put((size_t)3 * d.DH * d.KP * es);
-    w.BcT = put((size_t)3 * d.DH * d.KP * es);
+    w.BcT = put((size_t)round_up(3 * d.DH, d.prec == VMC_BF16 ? 32 : 16) * d.KP * es);
     w.Bg = put((size_t)2 * d.DH * KGP * es);
     w.BgT = put((size_t)2 * d.DH * KGP * es);
     w.E = put((size_t)ESLOTS * d.DH * 4);

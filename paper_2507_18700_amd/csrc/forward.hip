@@ -19,32 +19,6 @@
 
 namespace vmc {
 
-__host__ __device__ constexpr int cround(int x, int m) { return (x + m - 1) / m * m; }
-
-template <class P, int DIMS, int DH>
-struct FwdCfg {
-    static constexpr int NW = 4;
-    static constexpr int WU = (DH / 16 < NW) ? DH / 16 : NW;  // waves along hidden units
-    static constexpr int WR = NW / WU;                        // waves along rows
-    static constexpr int UW = DH / WU;                        // units per wave
-    static constexpr int UB = UW / 16;                        // 16-unit blocks per wave
-    static constexpr int MT = (DH >= 256) ? 32 : 64;          // rows per tile
-    static constexpr int RW = MT / WR;                        // rows per wave
-    static constexpr int RB = RW / 16;
-    static constexpr int K = DIMS == 1 ? DH : 2 * DH;
-    static constexpr int KP = cround(K, P::KSTEP);
-    static constexpr int KGP = cround(DH, P::KSTEP);
-    static constexpr int PADE = 16 / (int)sizeof(typename P::store_t);
-    static constexpr int SA_LD = KP + PADE;
-    static constexpr int SH_LD = KGP + PADE;
-};
-
-template <class P, int DIMS, int DH>
-int fwd_tile_rows() { return FwdCfg<P, DIMS, DH>::MT; }
-
-// Row width of the activation store (floats): gates, GLU a1, a2, g, 4 logits.
-__host__ __device__ inline int act_width(int dims, int DH) { return (nact_per_unit(dims) + 3) * DH + 4; }
-
 // ------------------------------------------------------------------ staging
 
 // Builds the MFMA-ready padded copies of the parameters (see common.h).
@@ -52,12 +26,13 @@ template <class P>
 __global__ void stage_weights(Dims d, const float *__restrict__ prm, typename P::store_t *Bc,
                               typename P::store_t *BcT, typename P::store_t *Bg,
                               typename P::store_t *BgT, float *E, float *Hd, float *hc, int KP,
-                              int KGP) {
+                              int KGP, int NCP) {
     typedef typename P::store_t T;
     const int dh = d.dh, DH = d.DH;
     ParamLayout L = param_layout(d.dims, dh, d.glu, d.cplx);
     const int64_t nBc = (int64_t)3 * DH * KP, nBg = (int64_t)2 * DH * KGP, nE = (int64_t)ESLOTS * DH;
-    const int64_t total = nBc + nBg + nE + 4 * DH + 4;
+    const int64_t nBcT = (int64_t)KP * NCP;
+    const int64_t total = nBc + nBg + nE + 4 * DH + 4 + nBcT;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = e;
@@ -82,9 +57,7 @@ __global__ void stage_weights(Dims d, const float *__restrict__ prm, typename P:
                     }
                 }
             }
-            T t = P::from_float(v);
-            Bc[(int64_t)n * KP + k] = t;
-            BcT[(int64_t)k * 3 * DH + n] = t;
+            Bc[(int64_t)n * KP + k] = P::from_float(v);
             continue;
         }
         r -= nBc;
@@ -139,6 +112,32 @@ __global__ void stage_weights(Dims d, const float *__restrict__ prm, typename P:
             continue;
         }
         r -= nE;
+        if (r >= 4 * DH + 4) {
+            // transposed cell weights [KP][NCP], contraction over n = gate*DH + unit
+            r -= 4 * DH + 4;
+            int k = (int)(r / NCP), n = (int)(r % NCP);
+            float v = 0.0f;
+            int g = n / DH, u = n % DH;
+            if (n < 3 * DH && u < dh) {
+                if (d.dims == 1) {
+                    if (k < dh) {
+                        if (g == 0) v = prm[L.Wg + (int64_t)u * (dh + 2) + k];
+                        else if (g == 1) v = prm[L.Wr + (int64_t)u * (dh + 2) + k];
+                        else v = prm[L.Wh + (int64_t)u * dh + k];
+                    }
+                } else {
+                    int kb = k / DH, kk = k % DH;
+                    if (kb < 2 && kk < dh) {
+                        int src = kb * dh + kk;
+                        if (g == 0) v = prm[L.W + (int64_t)u * (2 * dh + 4) + src];
+                        else if (g == 1) v = prm[L.Wg + (int64_t)u * (2 * dh + 4) + src];
+                        else v = prm[L.U + (int64_t)u * 2 * dh + src];
+                    }
+                }
+            }
+            BcT[(int64_t)k * NCP + n] = P::from_float(v);
+            continue;
+        }
         if (r < 4 * DH) {
             int o = (int)(r / DH), u = (int)(r % DH);
             float v = 0.0f;
@@ -759,15 +758,17 @@ int forward_tile_rows(int DH) { return DH >= 256 ? 32 : 64; }
 hipError_t launch_stage(const Dims &d, const float *prm, void *Bc, void *BcT, void *Bg, void *BgT,
                         float *E, float *Hd, float *hc, hipStream_t st) {
     int KGP = d.prec == VMC_BF16 ? cround(d.DH, 32) : cround(d.DH, 16);
-    int64_t n = (int64_t)3 * d.DH * d.KP + (int64_t)2 * d.DH * KGP + ESLOTS * d.DH + 4 * d.DH + 4;
+    int NCP = d.prec == VMC_BF16 ? cround(3 * d.DH, 32) : cround(3 * d.DH, 16);
+    int64_t n = (int64_t)3 * d.DH * d.KP + (int64_t)2 * d.DH * KGP + ESLOTS * d.DH + 4 * d.DH + 4 +
+                (int64_t)d.KP * NCP;
     int grid = (int)((n + 255) / 256);
     if (grid > 4096) grid = 4096;
     if (d.prec == VMC_BF16)
         hipLaunchKernelGGL(stage_weights<BF16>, dim3(grid), dim3(256), 0, st, d, prm, (uint16_t *)Bc,
-                           (uint16_t *)BcT, (uint16_t *)Bg, (uint16_t *)BgT, E, Hd, hc, d.KP, KGP);
+                           (uint16_t *)BcT, (uint16_t *)Bg, (uint16_t *)BgT, E, Hd, hc, d.KP, KGP, NCP);
     else
         hipLaunchKernelGGL(stage_weights<F32>, dim3(grid), dim3(256), 0, st, d, prm, (float *)Bc,
-                           (float *)BcT, (float *)Bg, (float *)BgT, E, Hd, hc, d.KP, KGP);
+                           (float *)BcT, (float *)Bg, (float *)BgT, E, Hd, hc, d.KP, KGP, NCP);
     return hipGetLastError();
 }
 

@@ -1,20 +1,655 @@
-// Backward pass (placeholder until the BPTT kernels land).
+// Energy gradient of VMC (Sec. III): FP64 statistics of the local energies,
+// a reverse sweep (backpropagation through the autoregressive chain) that
+// produces the per-(position, sample) deltas of every contraction, and the
+// weight gradients as contractions of those deltas with the layer inputs over
+// all (position, sample) rows: FP32 tile partials on MFMA, summed across tiles
+// in FP64 in a fixed order.
+//
+// With E held constant, the gradient is that of the surrogate
+//   L = sum_s [a_s log P(sigma_s) + b_s phi(sigma_s)],
+//   a_s = w_s Re(E_s - Ebar), b_s = 2 w_s Im(E_s - Ebar),
+// i.e. 2 Re sum_s w_s conj(E_s - Ebar) d log psi(sigma_s) with
+// d log psi = d log P / 2 + i d phi (Eq. 4).
 #include "kernels.h"
 
 namespace vmc {
 
+constexpr int DW_TILE = 64;     // output tile of the weight-gradient contraction
+constexpr int DW_ROWS = 4096;   // rows per FP32 partial (summed in FP64 afterwards)
+
+// ------------------------------------------------------------- statistics
+
+// One work-group: Ebar = sum w E, var = sum w |E - Ebar|^2, non-finite count.
+// Fixed per-thread strides and a fixed tree: bitwise reproducible.
+__global__ __launch_bounds__(1024) void stats_kernel(int64_t ns, const double *eloc, const double *w,
+                                                     double *stats) {
+    __shared__ double s0[1024], s1[1024], s2[1024];
+    const int t = threadIdx.x;
+    double er = 0.0, ei = 0.0, bad = 0.0;
+    for (int64_t s = t; s < ns; s += 1024) {
+        double ws = w ? w[s] : 1.0 / (double)ns;
+        double a = eloc[2 * s], b = eloc[2 * s + 1];
+        if (!isfinite(a) || !isfinite(b)) bad += 1.0;
+        er += ws * a;
+        ei += ws * b;
+    }
+    s0[t] = er;
+    s1[t] = ei;
+    s2[t] = bad;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if (t < h) {
+            s0[t] += s0[t + h];
+            s1[t] += s1[t + h];
+            s2[t] += s2[t + h];
+        }
+        __syncthreads();
+    }
+    const double Er = s0[0], Ei = s1[0], nbad = s2[0];
+    __syncthreads();
+    double v = 0.0;
+    for (int64_t s = t; s < ns; s += 1024) {
+        double ws = w ? w[s] : 1.0 / (double)ns;
+        double a = eloc[2 * s] - Er, b = eloc[2 * s + 1] - Ei;
+        v += ws * (a * a + b * b);
+    }
+    s0[t] = v;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if (t < h) s0[t] += s0[t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        stats[0] = Er;
+        stats[1] = Ei;
+        stats[2] = s0[0];
+        stats[3] = nbad;
+    }
+}
+
+// ------------------------------------------------------------ reverse sweep
+
+struct BwdArgs {
+    Dims d;
+    const void *BcT, *BgT;
+    const float *E, *Hd;
+    int64_t ns;
+    const uint8_t *cfg;
+    const float *hcache, *act;
+    const double *eloc, *w, *stats;
+    float *dcell, *dglu, *dhead;
+    float *dcol;  // [grid][Lx][MT][DH]
+};
+
+// Reverse sweep over the order positions for a tile of samples.  At each
+// position: head deltas (softmax / softsign derivatives, Eqs. 3, 5), GLU
+// deltas and their input gradient (MFMA), the gate deltas of the cell
+// (App. A) and their input gradient (MFMA), which is routed to the one or two
+// predecessor positions (carried in registers, or parked per column for the
+// vertical predecessor in 2D).
+template <class P, int DIMS, int DH>
+__global__ __launch_bounds__(256) void rnn_backward(BwdArgs a) {
+    typedef FwdCfg<P, DIMS, DH> C;
+    typedef typename P::store_t T;
+    constexpr int MT = C::MT, RB = C::RB, UB = C::UB, NCP = C::NCP, VEC = P::VEC, KSTEP = P::KSTEP;
+    constexpr int PADE = C::PADE;
+    // the GLU deltas (2*DH columns) and the cell deltas (3*DH columns) share
+    // one LDS tile with one row stride; columns >= 3*DH stay zero
+    constexpr int D3_LD = NCP + PADE, D2_LD = D3_LD;
+    constexpr int NA = DIMS == 1 ? 4 : 3;
+    constexpr int NDC = DIMS == 1 ? 4 * DH : 3 * DH;  // stored cell-delta width
+    constexpr int NOB = DIMS == 1 ? UB : 2 * UB;      // output column blocks of the cell dX
+
+    __shared__ __align__(16) T sDb[MT * D3_LD];
+    T *const sD3 = sDb;
+    T *const sD2 = sDb;
+    __shared__ float sDL[MT][4];
+    __shared__ float sCoef[MT][2];
+    __shared__ int sRow[MT];
+    extern __shared__ uint8_t sSig[];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w / C::WU, wu = w % C::WU;
+    const int N = a.d.N, Lx = a.d.Lx, Ly = a.d.Ly;
+    const int cplx = a.d.cplx, glu = a.d.glu;
+    const int64_t ns = a.ns;
+    const int AW = act_width(DIMS, DH);
+    const T *__restrict__ BcT = (const T *)a.BcT;
+    const T *__restrict__ BgT = (const T *)a.BgT;
+    const float *__restrict__ E = a.E;
+    const float *__restrict__ Hd = a.Hd;
+    float *dcol = a.dcol + (int64_t)blockIdx.x * Lx * MT * DH;
+
+    const int64_t e0 = (int64_t)blockIdx.x * MT;
+    const int nrow = (int)min((int64_t)MT, ns - e0);
+    if (tid < MT) {
+        int s = tid < nrow ? (int)(e0 + tid) : -1;
+        sRow[tid] = s;
+        float ca = 0.f, cb = 0.f;
+        if (s >= 0) {
+            const double ws = a.w ? a.w[s] : 1.0 / (double)ns;
+            ca = (float)(ws * (a.eloc[2 * s] - a.stats[0]));
+            cb = (float)(2.0 * ws * (a.eloc[2 * s + 1] - a.stats[1]));
+        }
+        sCoef[tid][0] = ca;
+        sCoef[tid][1] = cb;
+    }
+    for (int e = tid; e < MT * D3_LD; e += blockDim.x) sDb[e] = P::from_float(0.f);
+    __syncthreads();
+    for (int e = tid; e < MT * N; e += blockDim.x) {
+        int r = e / N, c = e - r * N;
+        int s = sRow[r];
+        sSig[e] = s >= 0 ? a.cfg[(int64_t)s * N + c] : (uint8_t)0;
+    }
+
+    float carry[RB][UB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+        for (int ub = 0; ub < UB; ub++)
+#pragma unroll
+            for (int ii = 0; ii < 4; ii++) carry[rb][ub][ii] = 0.f;
+    __syncthreads();
+
+    for (int q = N - 1; q >= 0; q--) {
+        const int site = order_site(q, Lx);
+        const int jrow = q / Lx, icol = site - jrow * Lx;
+        const bool row_start = (q % Lx) == 0;
+        const bool last_in_row = ((q + 1) % Lx) == 0;
+        const bool has_vt = DIMS == 2 && jrow > 0;
+        const bool vt_succ_parked = DIMS == 2 && jrow + 1 < Ly && !last_in_row;
+
+        // (a) head deltas
+        if (tid < MT) {
+            const int s = sRow[tid];
+            float d0 = 0.f, d1 = 0.f, z0 = 0.f, z1 = 0.f;
+            if (s >= 0) {
+                const float *ar = a.act + ((int64_t)q * ns + s) * AW + (NA + 3) * DH;
+                const float l0 = ar[0], l1 = ar[1];
+                const int sg = sSig[tid * N + site];
+                const float p1 = 1.0f / (1.0f + expf(l0 - l1));  // softmax(l)[1]
+                const float p0 = 1.0f - p1;
+                const float ca = sCoef[tid][0];
+                d0 = ca * ((sg == 0 ? 1.f : 0.f) - p0);
+                d1 = ca * ((sg == 1 ? 1.f : 0.f) - p1);
+                if (cplx) {
+                    const float z = sg ? ar[3] : ar[2];
+                    const float den = 1.0f + fabsf(z);
+                    const float dz = sCoef[tid][1] * PI_F / (den * den);
+                    if (sg) z1 = dz;
+                    else z0 = dz;
+                }
+                float *dh = a.dhead + ((int64_t)q * ns + s) * 4;
+                dh[0] = d0;
+                dh[1] = d1;
+                dh[2] = z0;
+                dh[3] = z1;
+            }
+            sDL[tid][0] = d0;
+            sDL[tid][1] = d1;
+            sDL[tid][2] = z0;
+            sDL[tid][3] = z1;
+        }
+        __syncthreads();
+
+        // (b) head -> g, GLU deltas
+        float dgv[RB][UB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+            for (int ii = 0; ii < 4; ii++) {
+                const int r = wr * C::RW + rb * 16 + 4 * (lane >> 4) + ii;
+                const int s = sRow[r];
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    const int u = wu * C::UW + ub * 16 + (lane & 15);
+                    float dg = Hd[u] * sDL[r][0] + Hd[DH + u] * sDL[r][1] + Hd[2 * DH + u] * sDL[r][2] +
+                               Hd[3 * DH + u] * sDL[r][3];
+                    dgv[rb][ub][ii] = dg;
+                    if (glu) {
+                        float d1 = 0.f, d2 = 0.f;
+                        if (s >= 0) {
+                            const float *ar = a.act + ((int64_t)q * ns + s) * AW + NA * DH;
+                            const float a1 = ar[u], a2 = ar[DH + u];
+                            const float sg2 = sigmoidf_(a2);
+                            d1 = dg * sg2;
+                            d2 = dg * a1 * sg2 * (1.0f - sg2);
+                            float *gd = a.dglu + ((int64_t)q * ns + s) * 2 * DH;
+                            gd[u] = d1;
+                            gd[DH + u] = d2;
+                        }
+                        sD2[r * D2_LD + u] = P::from_float(d1);
+                        sD2[r * D2_LD + DH + u] = P::from_float(d2);
+                    }
+                }
+            }
+        __syncthreads();
+
+        // (c) GLU input gradient: dh_glu = [d1 | d2] . [W_1 ; W_2]  (MFMA)
+        f32x4_t accg[RB][UB];
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+            for (int ub = 0; ub < UB; ub++) accg[rb][ub] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        if (glu) {
+#pragma unroll 2
+            for (int kk = 0; kk < 2 * DH; kk += KSTEP) {
+                uint4 af[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++) {
+                    int row = wr * C::RW + rb * 16 + (lane & 15);
+                    af[rb] = *(const uint4 *)&sD2[row * D2_LD + kk + VEC * (lane >> 4)];
+                }
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    int k = wu * C::UW + ub * 16 + (lane & 15);
+                    uint4 bf = *(const uint4 *)&BgT[(int64_t)k * 2 * DH + kk + VEC * (lane >> 4)];
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++) P::mma(accg[rb][ub], af[rb], bf);
+                }
+            }
+        }
+
+        __syncthreads();  // the GLU deltas are read before the cell deltas overwrite them
+
+        // (d) total dh and the cell deltas (App. A gate algebra, reversed)
+        float direct[RB][UB][4];  // 1D: dh (1-u), the gradient reaching h_{n-1} directly
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+            for (int ii = 0; ii < 4; ii++) {
+                const int r = wr * C::RW + rb * 16 + 4 * (lane >> 4) + ii;
+                const int s = sRow[r];
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    const int u = wu * C::UW + ub * 16 + (lane & 15);
+                    float dh = (glu ? accg[rb][ub][ii] : dgv[rb][ub][ii]) + carry[rb][ub][ii];
+                    if (vt_succ_parked) dh += dcol[((int64_t)icol * MT + r) * DH + u];
+                    float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+                    direct[rb][ub][ii] = 0.f;
+                    if (s >= 0) {
+                        const float *ar = a.act + ((int64_t)q * ns + s) * AW;
+                        if (DIMS == 1) {
+                            const float uu = ar[u], rr = ar[DH + u], m = ar[2 * DH + u], c = ar[3 * DH + u];
+                            const float hp = q > 0 ? a.hcache[((int64_t)(q - 1) * ns + s) * DH + u] : 0.f;
+                            const float du = dh * (c - hp), dc = dh * uu;
+                            const float dac = dc * (1.0f - c * c);
+                            g0 = du * uu * (1.0f - uu);     // pre-activation of u
+                            g1 = dac * m * rr * (1.0f - rr); // pre-activation of r
+                            g2 = dac * rr;                  // W_h h + b_h
+                            g3 = dac;                       // candidate pre-activation
+                            direct[rb][ub][ii] = dh * (1.0f - uu);
+                        } else {
+                            const float c = ar[u], uu = ar[DH + u], v = ar[2 * DH + u];
+                            const float du = dh * (c - v), dc = dh * uu;
+                            g0 = dc * (1.0f - c * c);       // candidate pre-activation
+                            g1 = du * uu * (1.0f - uu);     // update-gate pre-activation
+                            g2 = dh * (1.0f - uu);          // U h'
+                        }
+                        float *cd = a.dcell + ((int64_t)q * ns + s) * NDC;
+                        cd[u] = g0;
+                        cd[DH + u] = g1;
+                        cd[2 * DH + u] = g2;
+                        if (DIMS == 1) cd[3 * DH + u] = g3;
+                    }
+                    sD3[r * D3_LD + u] = P::from_float(g0);
+                    sD3[r * D3_LD + DH + u] = P::from_float(g1);
+                    sD3[r * D3_LD + 2 * DH + u] = P::from_float(g2);
+                }
+            }
+        __syncthreads();
+
+        // (e) cell input gradient: dA = delta . B_c  (MFMA); route to predecessors
+        f32x4_t accx[RB][NOB];
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+            for (int c = 0; c < NOB; c++) accx[rb][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+        for (int kk = 0; kk < NCP; kk += KSTEP) {
+            uint4 af[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++) {
+                int row = wr * C::RW + rb * 16 + (lane & 15);
+                af[rb] = *(const uint4 *)&sD3[row * D3_LD + kk + VEC * (lane >> 4)];
+            }
+#pragma unroll
+            for (int c = 0; c < NOB; c++) {
+                const int half = c / UB, ub = c % UB;
+                const int k = half * DH + wu * C::UW + ub * 16 + (lane & 15);
+                uint4 bf = *(const uint4 *)&BcT[(int64_t)k * NCP + kk + VEC * (lane >> 4)];
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++) P::mma(accx[rb][c], af[rb], bf);
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+            for (int ii = 0; ii < 4; ii++) {
+                const int r = wr * C::RW + rb * 16 + 4 * (lane >> 4) + ii;
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    const int u = wu * C::UW + ub * 16 + (lane & 15);
+                    if (DIMS == 1) {
+                        carry[rb][ub][ii] = accx[rb][ub][ii] + direct[rb][ub][ii];
+                    } else {
+                        const float dhz = accx[rb][ub][ii], dvt = accx[rb][UB + ub][ii];
+                        if (row_start) {
+                            carry[rb][ub][ii] = has_vt ? dvt : 0.f;
+                        } else {
+                            carry[rb][ub][ii] = dhz;
+                            if (has_vt) dcol[((int64_t)icol * MT + r) * DH + u] = dvt;
+                        }
+                    }
+                }
+            }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------- weight-gradient contraction
+
+struct DwArgs {
+    Dims d;
+    int seg;             // 0 cell, 1 GLU, 2 heads
+    int64_t ns, R;       // R = N * ns rows, row = q * ns + s
+    const float *D;      // [R][MD] deltas
+    int MD, Mp, Kp;      // delta row width, padded output dims
+    const float *hcache, *act;
+    const uint8_t *cfg;
+    float *part;         // [G][Mp][Kp]
+};
+
+// Input row of the contraction for segment `seg` at row (q, s), column k:
+//  cell 1D: [h_{q-1} | 1 | onehot(sigma_{q-1})]
+//  cell 2D: [h_hz | h_vt | 1 | onehot_hz | onehot_vt]
+//  GLU:     [h_q | 1];   heads: [g_q | 1]
+__device__ inline float dw_input(const DwArgs &a, int q, int s, int k) {
+    const int DH = a.d.DH, Lx = a.d.Lx, N = a.d.N;
+    const int64_t ns = a.ns;
+    if (a.seg == 1) {
+        if (k < DH) return a.hcache[((int64_t)q * ns + s) * DH + k];
+        return k == DH ? 1.f : 0.f;
+    }
+    if (a.seg == 2) {
+        if (k < DH) {
+            const int AW = act_width(a.d.dims, DH);
+            return a.act[((int64_t)q * ns + s) * AW + (nact_per_unit(a.d.dims) + 2) * DH + k];
+        }
+        return k == DH ? 1.f : 0.f;
+    }
+    const bool has_hz = (q % Lx) != 0;
+    if (a.d.dims == 1) {
+        if (k < DH) return has_hz ? a.hcache[((int64_t)(q - 1) * ns + s) * DH + k] : 0.f;
+        if (k == DH) return 1.f;
+        if (k <= DH + 2) return (has_hz && a.cfg[(int64_t)s * N + (q - 1)] == k - DH - 1) ? 1.f : 0.f;
+        return 0.f;
+    }
+    const int site = order_site(q, Lx);
+    const int jrow = q / Lx;
+    const bool has_vt = jrow > 0;
+    if (k < DH) return has_hz ? a.hcache[((int64_t)(q - 1) * ns + s) * DH + k] : 0.f;
+    if (k < 2 * DH) {
+        if (!has_vt) return 0.f;
+        const int pv = site_pos(site - Lx, Lx);
+        return a.hcache[((int64_t)pv * ns + s) * DH + (k - DH)];
+    }
+    if (k == 2 * DH) return 1.f;
+    if (k <= 2 * DH + 2)
+        return (has_hz && a.cfg[(int64_t)s * N + order_site(q - 1, Lx)] == k - 2 * DH - 1) ? 1.f : 0.f;
+    if (k <= 2 * DH + 4) return (has_vt && a.cfg[(int64_t)s * N + site - Lx] == k - 2 * DH - 3) ? 1.f : 0.f;
+    return 0.f;
+}
+
+// dW[m][k] partial over DW_ROWS rows: FP32 MFMA 16x16x4, 64x64 output tile,
+// 4 waves as 2x2 of 32x32.  Grid (m tiles, k tiles, row chunks).
+__global__ __launch_bounds__(256) void dw_kernel(DwArgs a) {
+    constexpr int RS = 32, LD = DW_TILE + 4;
+    __shared__ float sD[RS][LD], sX[RS][LD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.x * DW_TILE, k0 = blockIdx.y * DW_TILE;
+    const int64_t r0 = (int64_t)blockIdx.z * DW_ROWS;
+    const int64_t r1 = min(r0 + DW_ROWS, a.R);
+    const int wm = (w >> 1) * 32, wk = (w & 1) * 32;
+    f32x4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int64_t rb = r0; rb < r1; rb += RS) {
+        for (int e = tid; e < RS * DW_TILE; e += 256) {
+            const int rr = e / DW_TILE, c = e % DW_TILE;
+            const int64_t row = rb + rr;
+            float dv = 0.f, xv = 0.f;
+            if (row < r1) {
+                const int q = (int)(row / a.ns), s = (int)(row % a.ns);
+                const int m = m0 + c, k = k0 + c;
+                if (m < a.MD) dv = a.D[row * a.MD + m];
+                xv = dw_input(a, q, s, k);
+            }
+            sD[rr][c] = dv;
+            sX[rr][c] = xv;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < RS; kk += 4) {
+#pragma unroll
+            for (int i = 0; i < 2; i++) {
+                const float av = sD[kk + (lane >> 4)][wm + i * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    const float bv = sX[kk + (lane >> 4)][wk + j * 16 + (lane & 15)];
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float *out = a.part + (int64_t)blockIdx.z * a.Mp * a.Kp;
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int ii = 0; ii < 4; ii++) {
+                const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + ii;
+                const int k = k0 + wk + j * 16 + (lane & 15);
+                out[(int64_t)m * a.Kp + k] = acc[i][j][ii];
+            }
+}
+
+// Flat parameter index of the weight-gradient entry (seg, m, k), or -1 for
+// padding and unused combinations.
+__device__ inline int64_t dw_param(const Dims &d, int seg, int m, int k) {
+    const int dh = d.dh, DH = d.DH;
+    const ParamLayout L = param_layout(d.dims, dh, d.glu, d.cplx);
+    if (seg == 2) {
+        if (m >= 4 || (m >= 2 && !d.cplx)) return -1;
+        if (k < DH) {
+            if (k >= dh) return -1;
+            return m < 2 ? L.Ua + (int64_t)m * dh + k : L.Up + (int64_t)(m - 2) * dh + k;
+        }
+        if (k == DH) return m < 2 ? L.ca + m : L.cp + (m - 2);
+        return -1;
+    }
+    if (seg == 1) {
+        if (!d.glu || m >= 2 * DH) return -1;
+        const int half = m / DH, u = m % DH;
+        if (u >= dh) return -1;
+        if (k < DH) return k < dh ? (half ? L.W2 : L.W1) + (int64_t)u * dh + k : -1;
+        if (k == DH) return (half ? L.b2 : L.b1) + u;
+        return -1;
+    }
+    const int g = m / DH, u = m % DH;
+    if (u >= dh) return -1;
+    if (d.dims == 1) {
+        if (g > 3) return -1;
+        const int64_t rowg = L.Wg + (int64_t)u * (dh + 2), rowr = L.Wr + (int64_t)u * (dh + 2);
+        if (k < DH) {
+            if (k >= dh) return -1;
+            if (g == 0) return rowg + k;
+            if (g == 1) return rowr + k;
+            if (g == 2) return L.Wh + (int64_t)u * dh + k;
+            return -1;
+        }
+        if (k == DH) return g == 0 ? L.bg + u : g == 1 ? L.br + u : g == 2 ? L.bh + u : L.bin + u;
+        if (k <= DH + 2) {
+            const int c = k - DH - 1;
+            if (g == 0) return rowg + dh + c;
+            if (g == 1) return rowr + dh + c;
+            if (g == 3) return L.Win + (int64_t)u * 2 + c;
+            return -1;
+        }
+        return -1;
+    }
+    if (g > 2) return -1;
+    const int64_t row = g == 0 ? L.W + (int64_t)u * (2 * dh + 4)
+                      : g == 1 ? L.Wg + (int64_t)u * (2 * dh + 4)
+                               : L.U + (int64_t)u * 2 * dh;
+    if (k < DH) return k < dh ? row + k : -1;
+    if (k < 2 * DH) return (k - DH) < dh ? row + dh + (k - DH) : -1;
+    if (g == 2) return -1;
+    if (k == 2 * DH) return g == 0 ? L.b + u : L.bg + u;
+    if (k <= 2 * DH + 4) return row + 2 * dh + (k - 2 * DH - 1);
+    return -1;
+}
+
+// FP64 sum of the partials over the row chunks (fixed order), scattered into
+// the flat gradient.
+__global__ void dw_reduce(Dims d, int seg, const float *part, int G, int Mp, int Kp, double *grad) {
+    const int64_t n = (int64_t)Mp * Kp;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int m = (int)(e / Kp), k = (int)(e % Kp);
+        const int64_t idx = dw_param(d, seg, m, k);
+        if (idx < 0) continue;
+        double s = 0.0;
+        for (int g = 0; g < G; g++) s += (double)part[(int64_t)g * n + e];
+        grad[idx] = s;
+    }
+}
+
+__global__ void fill_f64(double *p, int64_t n, double v) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = v;
+}
+
+// ------------------------------------------------------------------ host
+
+struct SegDims {
+    int MD, Mp, Kp;
+};
+
+static SegDims seg_dims(const Dims &d, int seg) {
+    SegDims s;
+    if (seg == 0) {
+        s.MD = d.dims == 1 ? 4 * d.DH : 3 * d.DH;
+        s.Kp = cround(d.dims == 1 ? d.DH + 3 : 2 * d.DH + 5, DW_TILE);
+    } else if (seg == 1) {
+        s.MD = 2 * d.DH;
+        s.Kp = cround(d.DH + 1, DW_TILE);
+    } else {
+        s.MD = 4;
+        s.Kp = cround(d.DH + 1, DW_TILE);
+    }
+    s.Mp = cround(s.MD, DW_TILE);
+    return s;
+}
+
 void grad_sizes(const Dims &d, int64_t ns, int *G, size_t *part_floats, size_t *gst_doubles) {
-    *G = 1;
-    *part_floats = 16;
+    const int64_t R = (int64_t)d.N * ns;
+    *G = (int)((R + DW_ROWS - 1) / DW_ROWS);
+    size_t mx = 0;
+    for (int seg = 0; seg < 3; seg++) {
+        SegDims s = seg_dims(d, seg);
+        size_t n = (size_t)s.Mp * s.Kp;
+        if (n > mx) mx = n;
+    }
+    *part_floats = (size_t)(*G) * mx;
     *gst_doubles = 16;
 }
+
+template <class P, int DIMS, int DH>
+static hipError_t launch_bwd_t(const BwdArgs &a, int grid, hipStream_t st) {
+    typedef FwdCfg<P, DIMS, DH> C;
+    size_t dyn = ((size_t)C::MT * a.d.N + 15) / 16 * 16;
+    hipError_t e = hipFuncSetAttribute((const void *)rnn_backward<P, DIMS, DH>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((rnn_backward<P, DIMS, DH>), dim3(grid), dim3(256), dyn, st, a);
+    return hipGetLastError();
+}
+
+template <class P, int DIMS>
+static hipError_t launch_bwd_d(const BwdArgs &a, int grid, hipStream_t st) {
+    switch (a.d.DH) {
+        case 16: return launch_bwd_t<P, DIMS, 16>(a, grid, st);
+        case 32: return launch_bwd_t<P, DIMS, 32>(a, grid, st);
+        case 64: return launch_bwd_t<P, DIMS, 64>(a, grid, st);
+        case 128: return launch_bwd_t<P, DIMS, 128>(a, grid, st);
+        case 256: return launch_bwd_t<P, DIMS, 256>(a, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+int forward_tile_rows(int DH);
 
 hipError_t launch_grad(const Dims &d, const void *BcT, const void *BgT, const float *E, const float *Hd,
                        int64_t ns, const uint8_t *cfg, const float *hcache, const float *act,
                        const double *eloc, const double *weights, double *stats, float *dcell,
                        float *dglu, float *dhead, void *dcol, float *part, int G, double *grad_st,
                        double *grad, hipStream_t st) {
-    return hipErrorNotSupported;
+    hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(1024), 0, st, ns, eloc, weights, stats);
+    BwdArgs b;
+    b.d = d;
+    b.BcT = BcT;
+    b.BgT = BgT;
+    b.E = E;
+    b.Hd = Hd;
+    b.ns = ns;
+    b.cfg = cfg;
+    b.hcache = hcache;
+    b.act = act;
+    b.eloc = eloc;
+    b.w = weights;
+    b.stats = stats;
+    b.dcell = dcell;
+    b.dglu = dglu;
+    b.dhead = dhead;
+    b.dcol = (float *)dcol;
+    const int MT = forward_tile_rows(d.DH);
+    const int grid = (int)((ns + MT - 1) / MT);
+    hipError_t e;
+    if (d.prec == VMC_BF16)
+        e = d.dims == 1 ? launch_bwd_d<BF16, 1>(b, grid, st) : launch_bwd_d<BF16, 2>(b, grid, st);
+    else
+        e = d.dims == 1 ? launch_bwd_d<F32, 1>(b, grid, st) : launch_bwd_d<F32, 2>(b, grid, st);
+    if (e != hipSuccess) return e;
+    const int64_t P = param_layout(d.dims, d.dh, d.glu, d.cplx).total;
+    hipLaunchKernelGGL(fill_f64, dim3((int)((P + 255) / 256 < 4096 ? (P + 255) / 256 : 4096)), dim3(256), 0, st,
+                       grad, P, 0.0);
+    for (int seg = 0; seg < 3; seg++) {
+        if (seg == 1 && !d.glu) continue;
+        SegDims sd = seg_dims(d, seg);
+        DwArgs a;
+        a.d = d;
+        a.seg = seg;
+        a.ns = ns;
+        a.R = (int64_t)d.N * ns;
+        a.D = seg == 0 ? dcell : seg == 1 ? dglu : dhead;
+        a.MD = sd.MD;
+        a.Mp = sd.Mp;
+        a.Kp = sd.Kp;
+        a.hcache = hcache;
+        a.act = act;
+        a.cfg = cfg;
+        a.part = part;
+        dim3 grd(sd.Mp / DW_TILE, sd.Kp / DW_TILE, G);
+        hipLaunchKernelGGL(dw_kernel, grd, dim3(256), 0, st, a);
+        const int64_t n = (int64_t)sd.Mp * sd.Kp;
+        int rg = (int)((n + 255) / 256);
+        hipLaunchKernelGGL(dw_reduce, dim3(rg), dim3(256), 0, st, d, seg, part, G, sd.Mp, sd.Kp, grad);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace vmc

@@ -37,12 +37,36 @@ struct FwdArgs {
 
 enum { MODE_SAMPLE = 0, MODE_LOGPSI = 1, MODE_CHAIN = 2 };
 
-// number of activation floats per (position, sample) row stored for the backward
+__host__ __device__ constexpr int cround(int x, int m) { return (x + m - 1) / m * m; }
+
+// number of activation floats per unit stored for the backward: 1D (u, r, m, c), 2D (c, u, v)
 __host__ __device__ inline int nact_per_unit(int dims) { return dims == 1 ? 4 : 3; }
-// augmented cell-input width: [h_hz | h_vt] (K) + 1 + one-hots (2 or 4)
-__host__ __device__ inline int ain_width(int dims, int DH) {
-    return dims == 1 ? round_up(DH + 3, 16) : round_up(2 * DH + 5, 16);
-}
+
+// Tile shape of the row-tile kernels (forward engine and backward sweep):
+// 4 waves; waves split the hidden units (all three gate columns of a unit in
+// one lane) and, for small widths, the rows.
+template <class P, int DIMS, int DH>
+struct FwdCfg {
+    static constexpr int NW = 4;
+    static constexpr int WU = (DH / 16 < NW) ? DH / 16 : NW;  // waves along hidden units
+    static constexpr int WR = NW / WU;                        // waves along rows
+    static constexpr int UW = DH / WU;                        // units per wave
+    static constexpr int UB = UW / 16;                        // 16-unit blocks per wave
+    static constexpr int MT = (DH >= 256) ? 32 : 64;          // rows per tile
+    static constexpr int RW = MT / WR;                        // rows per wave
+    static constexpr int RB = RW / 16;
+    static constexpr int K = DIMS == 1 ? DH : 2 * DH;
+    static constexpr int KP = cround(K, P::KSTEP);
+    static constexpr int KGP = cround(DH, P::KSTEP);
+    static constexpr int PADE = 16 / (int)sizeof(typename P::store_t);
+    static constexpr int SA_LD = KP + PADE;
+    static constexpr int SH_LD = KGP + PADE;
+    static constexpr int NCP = cround(3 * DH, P::KSTEP);      // padded cell-delta width (backward)
+};
+
+// Row width of the activation store (floats): gates, GLU a1, a2, g, 4 logits.
+__host__ __device__ inline int act_width(int dims, int DH) { return (nact_per_unit(dims) + 3) * DH + 4; }
+
 
 // bonds of the open chain / square lattice in the order used everywhere:
 // for each site a = j*Lx+i in lattice order, the bond to (i+1,j) then (i,j+1)

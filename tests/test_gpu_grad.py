@@ -1,0 +1,130 @@
+"""GPU parity of vmc_grad: the hand-written backward sweep against the FP64
+oracle's reverse-mode gradient on identical configurations and local
+energies, the FP64 statistics, and directional finite differences of the
+GPU's own log psi.  FP32: 1e-5 relative (l2, with the cancellation factor
+kappa = sum|terms| / |sum| reported), BF16: 1e-2."""
+import numpy as np
+import pytest
+
+from paper_2507_18700_amd import synth
+from tests.gpu_util import lib_and_oracle, rel_l2, torch_gpu
+
+pytestmark = pytest.mark.gpu
+
+GRAD_CASES = [
+    (1, 20, 1, 16, False, False),
+    (1, 12, 1, 5, True, True),
+    (1, 30, 1, 32, True, False),
+    (1, 9, 1, 64, False, True),
+    (2, 4, 4, 16, False, True),
+    (2, 5, 3, 20, True, True),
+    (2, 4, 3, 64, True, False),
+    (2, 3, 3, 128, False, True),
+]
+
+
+def _ids(c):
+    return "%dD_%dx%d_dh%d_c%d_g%d" % c
+
+
+@pytest.mark.parametrize("case", GRAD_CASES, ids=_ids)
+@pytest.mark.parametrize("bf16", [False, True], ids=["fp32", "bf16"])
+def test_grad_parity(case, bf16):
+    torch = torch_gpu()
+    from oracle import oracle as O
+    from paper_2507_18700_amd import vmcrnn as V
+    dims, Lx, Ly, dh, cplx, glu = case
+    spec, gm, _ = lib_and_oracle(dims, Lx, Ly, dh, cplx, glu, bf16)
+    _, _, om = lib_and_oracle(dims, Lx, Ly, dh, cplx, glu, False)
+    p = synth.xavier_params(spec, 21, bias_scale=0.2)
+    ns = 97
+    cfg = synth.configs(ns, spec.N, 22)
+    e = synth.eloc_values(ns, 23, complex_=cplx, scale=2.0)
+    e[:, 0] -= 10.0
+    g, st = V.vmc_grad(gm, torch.from_numpy(p).cuda(), torch.from_numpy(cfg).cuda(),
+                       torch.from_numpy(e).cuda())
+    torch.cuda.synchronize()
+    g, st = g.cpu().numpy(), st.cpu().numpy()
+    rg, rst = O.grad(om, p.astype(np.float64), cfg, e)
+    assert np.allclose(st[:3], rst[:3], rtol=1e-13, atol=1e-13) and st[3] == 0
+    tol = 1e-2 if bf16 else 1e-5
+    err = rel_l2(g, rg)
+    assert err < tol, "relative l2 error %.3g" % err
+    # every block of the flat vector on its own
+    o = 0
+    for name, shape in synth.blocks(spec):
+        n = int(np.prod(shape))
+        ref = rg[o:o + n]
+        if np.linalg.norm(ref) > 1e-3 * np.linalg.norm(rg):
+            assert rel_l2(g[o:o + n], ref) < 10 * tol, name
+        o += n
+
+
+def test_grad_weights_and_determinism():
+    torch = torch_gpu()
+    from oracle import oracle as O
+    from paper_2507_18700_amd import vmcrnn as V
+    spec, gm, om = lib_and_oracle(2, 4, 4, 32, True, True)
+    p = synth.xavier_params(spec, 31, bias_scale=0.2)
+    ns = 150
+    cfg = synth.configs(ns, spec.N, 32)
+    e = synth.eloc_values(ns, 33, complex_=True)
+    w = np.random.default_rng(34).random(ns)
+    w /= w.sum()
+    args = (gm, torch.from_numpy(p).cuda(), torch.from_numpy(cfg).cuda(), torch.from_numpy(e).cuda())
+    g1, s1 = V.vmc_grad(*args, weights=torch.from_numpy(w).cuda())
+    g1, s1 = g1.clone(), s1.clone()
+    g2, s2 = V.vmc_grad(*args, weights=torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2) and torch.equal(s1, s2)
+    rg, rst = O.grad(om, p.astype(np.float64), cfg, e, w)
+    assert rel_l2(g1.cpu().numpy(), rg) < 1e-5
+    assert np.allclose(s1.cpu().numpy()[:3], rst[:3], rtol=1e-13, atol=1e-14)
+
+
+def test_grad_nonfinite_count():
+    torch = torch_gpu()
+    from paper_2507_18700_amd import vmcrnn as V
+    spec, gm, _ = lib_and_oracle(1, 8, 1, 16, False, False)
+    p = synth.xavier_params(spec, 41)
+    cfg = synth.configs(10, 8, 42)
+    e = synth.eloc_values(10, 43)
+    e[3, 0] = np.nan
+    e[7, 1] = np.inf
+    _, st = V.vmc_grad(gm, torch.from_numpy(p).cuda(), torch.from_numpy(cfg).cuda(), torch.from_numpy(e).cuda())
+    torch.cuda.synchronize()
+    assert st.cpu().numpy()[3] == 2
+
+
+@pytest.mark.parametrize("case", [GRAD_CASES[1], GRAD_CASES[5]], ids=_ids)
+def test_grad_directional_finite_differences(case):
+    """g . v against (L(p + eps v) - L(p - eps v)) / (2 eps) with the GPU's own
+    FP32 log psi, L = sum_s a_s logP_s + b_s phi_s."""
+    torch = torch_gpu()
+    from oracle import oracle as O
+    from paper_2507_18700_amd import vmcrnn as V
+    dims, Lx, Ly, dh, cplx, glu = case
+    spec, gm, _ = lib_and_oracle(dims, Lx, Ly, dh, cplx, glu)
+    p = synth.xavier_params(spec, 51, bias_scale=0.2)
+    ns = 64
+    cfg = synth.configs(ns, spec.N, 52)
+    e = synth.eloc_values(ns, 53, complex_=cplx)
+    cd = torch.from_numpy(cfg).cuda()
+    g, st = V.vmc_grad(gm, torch.from_numpy(p).cuda(), cd, torch.from_numpy(e).cuda())
+    g = g.cpu().numpy()
+    st = st.cpu().numpy()
+    a = (e[:, 0] - st[0]) / ns
+    b = 2 * (e[:, 1] - st[1]) / ns
+    rng = np.random.default_rng(54)
+    for _ in range(3):
+        v = rng.standard_normal(p.size)
+        v /= np.linalg.norm(v)
+        eps = 3e-3
+
+        def L(q):
+            lp, ph = V.rnn_logpsi(gm, torch.from_numpy(q.astype(np.float32)).cuda(), cd)
+            return float((a * lp.cpu().numpy().astype(np.float64)).sum() +
+                         (b * ph.cpu().numpy().astype(np.float64)).sum())
+
+        fd = (L(p + eps * v) - L(p - eps * v)) / (2 * eps)
+        assert abs(fd - g @ v) <= 2e-3 * max(abs(g @ v), 1e-2 * np.linalg.norm(g))
