@@ -1,0 +1,187 @@
+"""Throughput of one VMC step (sample + local energy + gradient) of the 2D GRU
+RNN wave function on one MI355X.
+
+Workload: 2D transverse-field Ising model on a 10x10 open square lattice,
+J = 1, h = 3; zig-zag 2D GRU with GLU, positive amplitudes; d_h = 64 weights
+(Xavier-uniform, seed 0) grown to d_h = 128 by grow_hidden (noise std 1e-3,
+seed 2); Ns = 10000 samples per step drawn with the on-device Philox stream
+(seed 1, counter = step).  A step is rnn_sample -> local_energy (all 100 spin
+flips of every sample in one launch) -> vmc_grad; inputs and parameters are
+resident in HBM before the timed region.
+
+Prints one JSON line.  `roofline` is for the dominant kernel (the batched
+suffix-chain launch of local_energy), timed with HIP events on its stream;
+`cpu_baseline` is the FP64 oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "VMC samples/s (sample+E_loc+grad), 2D RNN 10×10 d_h=128; BF16 vs FP32"
+LX = LY = 10
+N = LX * LY
+DH0, DH = 64, 128
+NS = 10000
+H_FIELD, J_COUP = 3.0, 1.0
+PEAK_TF = {"bf16": 2500.0, "fp32": 157.3}
+
+
+def site_flops(dh, n_out=2):
+    # 2D cell [2dh -> 3dh] + GLU [dh -> 2dh] + heads [dh -> n_out], 2 flops per MAC
+    return 2 * (2 * dh) * (3 * dh) + 2 * dh * (2 * dh) + 2 * dh * n_out
+
+
+def build_params(torch, V, synth):
+    spec0 = synth.ModelSpec(dims=2, Lx=LX, Ly=LY, d_h=DH0, glu=True)
+    p0 = torch.from_numpy(synth.xavier_params(spec0, 0)).cuda()
+    m0 = V.model(dims=2, Lx=LX, Ly=LY, d_h=DH0, glu=True)
+    p1, _ = V.grow_hidden(m0, p0, DH, 2, 1e-3)
+    return p1
+
+
+def run_gpu(torch, V, params, precision, steps, warmup):
+    m = V.model(dims=2, Lx=LX, Ly=LY, d_h=DH, glu=True,
+                precision=V.VMC_BF16 if precision == "bf16" else V.VMC_FP32)
+    H = V.ham(V.VMC_TFIM, J=J_COUP, h=H_FIELD)
+    ws = V.Workspace()
+    ws.get(V.workspace_size(m, H, NS))
+    dev = params.device
+    cfg = torch.empty((NS, N), dtype=torch.uint8, device=dev)
+    lp = torch.empty(NS, dtype=torch.float32, device=dev)
+    ph = torch.empty(NS, dtype=torch.float32, device=dev)
+    e = torch.empty((NS, 2), dtype=torch.float64, device=dev)
+    g = torch.empty(V.param_count(m), dtype=torch.float64, device=dev)
+    st = torch.empty(4, dtype=torch.float64, device=dev)
+
+    def step(i):
+        V.rnn_sample(m, params, NS, seed=1, counter=i, ws=ws, out=(cfg, lp, ph))
+        V.local_energy(m, params, H, cfg, ws=ws, out=e)
+        V.vmc_grad(m, params, cfg, e, ws=ws, out=(g, st))
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    V.chain_timing(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record()
+    for i in range(steps):
+        step(warmup + i)
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    chain_ms, launches = V.chain_time()
+    V.chain_timing(False)
+    ms = t0.elapsed_time(t1) / steps
+    # the configurations and energies of the last step, for the accuracy check
+    return dict(ms_per_step=ms, wall_s=wall, chain_ms=chain_ms / max(launches, 1), launches=launches,
+                cfg=cfg.clone(), e=e.clone(), stats=st.clone(), counter=warmup + steps - 1)
+
+
+def cpu_baseline(torch, params, cfg, e_gpu, n_sub):
+    """FP64 oracle (test infrastructure) on the first n_sub samples of the same
+    step: sampling from the same Philox uniforms, the local energy of every
+    sample and the gradient; also the energy-per-site error of the GPU."""
+    import numpy as np
+    from oracle import oracle as O
+    om = O.model(dims=2, Lx=LX, Ly=LY, d_h=DH, glu=True)
+    p = params.cpu().numpy().astype(np.float64)
+    c = cfg[:n_sub].cpu().numpy()
+    t = time.perf_counter()
+    uni = O.philox_uniforms(1, 0, n_sub, N)
+    O.sample(om, p, uni)
+    eo = O.local_energy(om, p, O.ham(O.TFIM, J=J_COUP, h=H_FIELD), c)
+    O.grad(om, p, c, eo)
+    dt = time.perf_counter() - t
+    eg = e_gpu[:n_sub].cpu().numpy()
+    err = abs(eg[:, 0].mean() - eo.real.mean()) / N
+    return dict(value=n_sub / dt, unit="samples/s", cores=O.num_threads(), kind="oracle",
+                sample="first %d of the %d samples of one step (FP64 sample + E_loc with full "
+                       "re-evaluation + gradient), %.1f s" % (n_sub, NS, dt)), err
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-samples", type=int, default=192)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2507_18700_amd import synth, vmcrnn as V
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    params = build_params(torch, V, synth)
+    torch.cuda.synchronize()
+    print("bench: params ready (%d floats), timing BF16 path" % params.numel(), file=sys.stderr, flush=True)
+    bf = run_gpu(torch, V, params, "bf16", args.steps, args.warmup)
+    print("bench: bf16 %.2f ms/step" % bf["ms_per_step"], file=sys.stderr, flush=True)
+    fp = None
+    if not args.no_fp32:
+        fp = run_gpu(torch, V, params, "fp32", max(1, min(args.steps, 3)), 1)
+        print("bench: fp32 %.2f ms/step" % fp["ms_per_step"], file=sys.stderr, flush=True)
+
+    flops_chain = NS * (N * (N - 1) // 2) * site_flops(DH)
+    flops_step = NS * (N + N * (N - 1) // 2 + 2 * N) * site_flops(DH)
+    achieved = flops_chain / (bf["chain_ms"] * 1e-3) / 1e12
+    value = NS / (bf["ms_per_step"] * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(bf["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "2D TFIM 10x10 open, J=1, h=3; zig-zag 2D GRU + GLU, positive RNN, "
+                               "d_h 64->128 via grow_hidden; Ns=10000 per step; sample + E_loc + grad",
+                   "Lx": LX, "Ly": LY, "d_h": DH, "ns": NS, "precision": "bf16 MFMA operands, fp32 accumulate, "
+                                                                         "fp64 cross-sample reductions"},
+        "roofline": {"bound": "mfma", "kernel": "rnn_forward<BF16,2,128> (suffix chains of local_energy)",
+                     "achieved": round(achieved, 2), "peak": PEAK_TF["bf16"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_TF["bf16"], 4), "traffic": None,
+                     "flops_per_launch": flops_chain, "avg_launch_ms": round(bf["chain_ms"], 3)},
+        "step_flops_algorithmic": flops_step,
+        "step_frac_of_bf16_peak": round(flops_step / (bf["ms_per_step"] * 1e-3) / 1e12 / PEAK_TF["bf16"], 4),
+    }
+    if fp is not None:
+        out["fp32"] = {"value": round(NS / (fp["ms_per_step"] * 1e-3), 1), "ms_per_step": round(fp["ms_per_step"], 3),
+                       "chain_avg_launch_ms": round(fp["chain_ms"], 3),
+                       "chain_frac_of_fp32_peak": round(flops_chain / (fp["chain_ms"] * 1e-3) / 1e12 / PEAK_TF["fp32"], 4),
+                       "bf16_speedup": round(fp["ms_per_step"] / bf["ms_per_step"], 3)}
+    if not args.no_cpu:
+        cb, err_bf = cpu_baseline(torch, params, bf["cfg"], bf["e"], args.cpu_samples)
+        out["cpu_baseline"] = cb
+        acc = {"energy_per_site_err_bf16": err_bf}
+        if fp is not None:
+            # same configurations through the FP32 path
+            m32 = V.model(dims=2, Lx=LX, Ly=LY, d_h=DH, glu=True, precision=V.VMC_FP32)
+            e32 = V.local_energy(m32, params, V.ham(V.VMC_TFIM, J=J_COUP, h=H_FIELD), bf["cfg"])
+            _, err32 = cpu_baseline(torch, params, bf["cfg"], e32, min(32, args.cpu_samples))
+            acc["energy_per_site_err_fp32_first32"] = err32
+        acc["reference"] = "FP64 oracle on the first samples of the last timed step"
+        out["accuracy"] = acc
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

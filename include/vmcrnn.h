@@ -143,6 +143,16 @@ vmc_status grow_hidden(const vmc_model *from, const float *p_from, int32_t new_d
                        double noise_std, float *p_to, const float *m_from, const float *v_from,
                        float *m_to, float *v_to, void *stream);
 
+/* Opt-in timing of the dominant launch, the batched suffix-chain kernel of
+ * local_energy.  vmc_chain_timing(1) creates (once) a pool of HIP events,
+ * resets the record and makes every following local_energy call record one
+ * event pair around that launch on its stream (up to 4096 launches);
+ * vmc_chain_timing(0) stops recording.  vmc_chain_time() waits for the
+ * recorded events and returns the summed milliseconds and the number of
+ * timed launches.  Process-wide; not meant for concurrent callers. */
+vmc_status vmc_chain_timing(int enable);
+vmc_status vmc_chain_time(double *ms_total, int64_t *launches);
+
 /* Static description of a status code. */
 const char *vmc_status_str(vmc_status s);
 

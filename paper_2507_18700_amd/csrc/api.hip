@@ -185,6 +185,14 @@ static FwdArgs base_args(const Dims &d, void *ws, const WsMap &w, int64_t ns) {
     return a;
 }
 
+// Event pairs around the suffix-chain launch (opt-in profiling).
+struct ChainTiming {
+    int enabled = 0, created = 0, n = 0;
+    static const int kMax = 4096;
+    hipEvent_t ev[2 * kMax];
+};
+static ChainTiming g_timing;
+
 }  // namespace vmc
 
 using namespace vmc;
@@ -287,8 +295,14 @@ vmc_status local_energy(const vmc_model *m, const float *params, const vmc_ham *
     a.NC = w.NC;
     a.logp = NULL;
     a.phase = NULL;
+    const bool timed = g_timing.enabled && g_timing.n < ChainTiming::kMax;
+    if (timed && hipEventRecord(g_timing.ev[2 * g_timing.n], st) != hipSuccess) return VMC_EDEVICE;
     e = launch_forward(a, MODE_CHAIN, 0, 0, 0, w.chain_grid, st);
     if (e != hipSuccess) return VMC_EDEVICE;
+    if (timed) {
+        if (hipEventRecord(g_timing.ev[2 * g_timing.n + 1], st) != hipSuccess) return VMC_EDEVICE;
+        g_timing.n++;
+    }
     // 4. assembly
     return hip_status(launch_assemble(*H, d.Lx, d.Ly, ns, configs, at<float>(ws, w.lpc), at<float>(ws, w.phc),
                                       at<float2>(ws, w.dsuf), w.NC, eloc, st));
@@ -333,6 +347,35 @@ vmc_status grow_hidden(const vmc_model *from, const float *p_from, int32_t new_d
     int64_t n_to = param_layout(to.dims, new_dh, to.glu, to.is_complex).total;
     return hip_status(launch_grow(*from, p_from, new_dh, seed, noise_std, p_to, m_from, v_from, m_to, v_to, n_to,
                                   (hipStream_t)stream));
+}
+
+vmc_status vmc_chain_timing(int enable) {
+    if (enable) {
+        if (!g_timing.created) {
+            for (int i = 0; i < 2 * ChainTiming::kMax; i++)
+                if (hipEventCreate(&g_timing.ev[i]) != hipSuccess) return VMC_EDEVICE;
+            g_timing.created = 1;
+        }
+        g_timing.n = 0;
+        g_timing.enabled = 1;
+    } else {
+        g_timing.enabled = 0;
+    }
+    return VMC_OK;
+}
+
+vmc_status vmc_chain_time(double *ms_total, int64_t *launches) {
+    if (!ms_total || !launches) return VMC_EINVAL;
+    double tot = 0.0;
+    for (int i = 0; i < g_timing.n; i++) {
+        float ms = 0.f;
+        if (hipEventSynchronize(g_timing.ev[2 * i + 1]) != hipSuccess) return VMC_EDEVICE;
+        if (hipEventElapsedTime(&ms, g_timing.ev[2 * i], g_timing.ev[2 * i + 1]) != hipSuccess) return VMC_EDEVICE;
+        tot += ms;
+    }
+    *ms_total = tot;
+    *launches = g_timing.n;
+    return VMC_OK;
 }
 
 const char *vmc_status_str(vmc_status s) {

@@ -17,7 +17,7 @@ VMC_FP32, VMC_BF16 = 0, 1
 VMC_TFIM, VMC_HEISENBERG = 0, 1
 
 EXPORTS = ("vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "local_energy",
-           "vmc_grad", "grow_hidden", "vmc_status_str")
+           "vmc_grad", "grow_hidden", "vmc_chain_timing", "vmc_chain_time", "vmc_status_str")
 
 
 class VmcError(RuntimeError):
@@ -76,6 +76,10 @@ def lib():
         L.vmc_grad.argtypes = [P(Model), vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
         L.grow_hidden.restype = ctypes.c_int
         L.grow_hidden.argtypes = [P(Model), vp, ctypes.c_int32, u64, d, vp, vp, vp, vp, vp, vp]
+        L.vmc_chain_timing.restype = ctypes.c_int
+        L.vmc_chain_timing.argtypes = [ctypes.c_int]
+        L.vmc_chain_time.restype = ctypes.c_int
+        L.vmc_chain_time.argtypes = [P(d), P(i64)]
         L.vmc_status_str.restype = ctypes.c_char_p
         L.vmc_status_str.argtypes = [ctypes.c_int]
         _lib = L
@@ -220,3 +224,16 @@ def grow_hidden(m, params, new_dh, seed, noise_std, m_mom=None, v_mom=None):
     if mm is not None:
         return p1, mm, vv, to
     return p1, to
+
+
+def chain_timing(enable):
+    """Start (and reset) or stop event timing of the suffix-chain launch."""
+    _check(lib().vmc_chain_timing(int(bool(enable))))
+
+
+def chain_time():
+    """(total milliseconds, number of timed launches) of the suffix-chain kernel."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().vmc_chain_time(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
