@@ -14,8 +14,9 @@ hipError_t launch_sched(int ham_kind, int Lx, int Ly, int64_t ns, const uint8_t 
                         int *list_off, int *list, int *tile_start, int *tile_counter, int MT,
                         hipStream_t st);
 hipError_t launch_assemble(const vmc_ham &H, int Lx, int Ly, int64_t ns, const uint8_t *cfg,
-                           const float *lpc, const float *phc, const float2 *dsuf, int NC, double *eloc,
-                           hipStream_t st);
+                           const float *lpc, const float *phc, const double2 *pre, const double2 *dsuf, int NC,
+                           double *eloc, hipStream_t st);
+int engine_kpx(const Dims &d);
 int forward_tile_rows(int DH);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
 hipError_t launch_grad(const Dims &d, const void *BcT, const void *BgT, const float *E, const float *Hd,
@@ -83,7 +84,7 @@ static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 // Workspace map; offsets in bytes from the workspace base.
 struct WsMap {
     size_t Bc, BcT, Bg, BgT, E, Hd, hc;
-    size_t hcache, lpc, phc, dsuf;
+    size_t hcache, lpc, phc, pre, dsuf;
     size_t cnt, list_off, tile_start, tile_counter, list;
     size_t colbuf;
     size_t act, dcell, dglu, dhead, dcol, part, gst, stats;
@@ -103,8 +104,8 @@ static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
         o += al(bytes);
         return at;
     };
-    w.Bc = put((size_t)3 * d.DH * d.KP * es);
-    w.BcT = put((size_t)round_up(3 * d.DH, d.prec == VMC_BF16 ? 32 : 16) * d.KP * es);
+    w.Bc = put((size_t)3 * d.DH * engine_kpx(d) * es);
+    w.BcT = put((size_t)round_up(3 * d.DH, d.prec == VMC_BF16 ? 32 : 16) * d.K * es);
     w.Bg = put((size_t)2 * d.DH * KGP * es);
     w.BgT = put((size_t)2 * d.DH * KGP * es);
     w.E = put((size_t)ESLOTS * d.DH * 4);
@@ -113,9 +114,10 @@ static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
     w.hcache = put((size_t)d.N * ns * d.DH * 4);
     w.lpc = put((size_t)ns * d.N * 2 * 4);
     w.phc = put((size_t)ns * d.N * 2 * 4);
+    w.pre = put((size_t)ns * d.N * 16);
     const int nb = bond_count(d.Lx, d.Ly);
     w.NC = (H && H->kind == VMC_HEISENBERG) ? nb : d.N;
-    w.dsuf = put((size_t)ns * w.NC * 8);
+    w.dsuf = put((size_t)ns * w.NC * 16);
     w.cnt = put((size_t)(d.N + 1) * 4);
     w.list_off = put((size_t)(d.N + 1) * 4);
     w.tile_start = put((size_t)(d.N + 1) * 4);
@@ -277,6 +279,7 @@ vmc_status local_energy(const vmc_model *m, const float *params, const vmc_ham *
     a.hcache = at<float>(ws, w.hcache);
     a.lpc = at<float>(ws, w.lpc);
     a.phc = at<float>(ws, w.phc);
+    a.pre = at<double2>(ws, w.pre);
     e = launch_forward(a, MODE_LOGPSI, 1, 1, 0, w.fwd_grid, st);
     if (e != hipSuccess) return VMC_EDEVICE;
     // 2. connection list and tile schedule
@@ -291,7 +294,7 @@ vmc_status local_energy(const vmc_model *m, const float *params, const vmc_ham *
     a.list_off = at<int>(ws, w.list_off);
     a.list = at<int>(ws, w.list);
     a.tile_counter = at<int>(ws, w.tile_counter);
-    a.dsuf = at<float2>(ws, w.dsuf);
+    a.dsuf = at<double2>(ws, w.dsuf);
     a.NC = w.NC;
     a.logp = NULL;
     a.phase = NULL;
@@ -305,7 +308,7 @@ vmc_status local_energy(const vmc_model *m, const float *params, const vmc_ham *
     }
     // 4. assembly
     return hip_status(launch_assemble(*H, d.Lx, d.Ly, ns, configs, at<float>(ws, w.lpc), at<float>(ws, w.phc),
-                                      at<float2>(ws, w.dsuf), w.NC, eloc, st));
+                                      at<double2>(ws, w.pre), at<double2>(ws, w.dsuf), w.NC, eloc, st));
 }
 
 vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const uint8_t *configs,

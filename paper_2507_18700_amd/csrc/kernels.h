@@ -21,6 +21,7 @@ struct FwdArgs {
     // caches (NULL = not written / not read)
     float *hcache;           // [N][ns][DH] fp32 hidden states
     float *lpc, *phc;        // [ns][N][2] log-conditionals, phase conditionals
+    double2 *pre;            // [ns][N] running (log P, phase) after each position, FP64
     float *act;              // [N][ns][NACT*DH] activations for the backward
     float *ain;              // [N][ns][KA] augmented cell inputs for the backward
     int64_t ns_cache;        // row count of the cache arrays
@@ -31,7 +32,7 @@ struct FwdArgs {
     int nbond;
     const int *cnt, *tile_start, *list_off, *list;
     int *tile_counter;
-    float2 *dsuf;            // [ns][NC] suffix sums (dlogP, dphi)
+    double2 *dsuf;           // [ns][NC] suffix sums of the connected chain (log P, phase)
     int NC;
 };
 
