@@ -5,9 +5,10 @@ Workload: 2D transverse-field Ising model on a 10x10 open square lattice,
 J = 1, h = 3; zig-zag 2D GRU with GLU, positive amplitudes; d_h = 64 weights
 (Xavier-uniform, seed 0) grown to d_h = 128 by grow_hidden (noise std 1e-3,
 seed 2); Ns = 10000 samples per step drawn with the on-device Philox stream
-(seed 1, counter = step).  A step is rnn_sample -> local_energy (all 100 spin
-flips of every sample in one launch) -> vmc_grad; inputs and parameters are
-resident in HBM before the timed region.
+(seed 1, counter = step).  A step is one vmc_step call: sampling, the local
+energy (all 100 spin flips of every sample in one launch) and the gradient,
+sharing one forward pass; parameters are resident in HBM before the timed
+region.
 
 Prints one JSON line.  `roofline` is for the dominant kernel (the batched
 suffix-chain launch of local_energy), timed with HIP events on its stream;
@@ -59,9 +60,7 @@ def run_gpu(torch, V, params, precision, steps, warmup):
     st = torch.empty(4, dtype=torch.float64, device=dev)
 
     def step(i):
-        V.rnn_sample(m, params, NS, seed=1, counter=i, ws=ws, out=(cfg, lp, ph))
-        V.local_energy(m, params, H, cfg, ws=ws, out=e)
-        V.vmc_grad(m, params, cfg, e, ws=ws, out=(g, st))
+        V.vmc_step(m, params, H, NS, seed=1, counter=i, ws=ws, out=(cfg, lp, ph, e, g, st))
 
     for i in range(warmup):
         step(i)

@@ -129,6 +129,17 @@ vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const u
                     const double *eloc, const double *weights, double *grad, double *stats,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* One VMC step in one call: rnn_sample, then local_energy of the samples,
+ * then vmc_grad with w_s = 1/ns, sharing one forward pass (the sampler keeps
+ * the hidden states, conditionals and activations that the local energy and
+ * the backward sweep need).  Outputs equal those of the three separate calls
+ * with the same arguments.  uniforms may be NULL (Philox as in rnn_sample);
+ * phase may be NULL. */
+vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns,
+                    uint64_t seed, uint64_t counter, const float *uniforms, uint8_t *configs,
+                    float *logp, float *phase, double *eloc, double *grad, double *stats,
+                    void *ws, size_t ws_bytes, void *stream);
+
 /* Adaptive growth of the hidden width (Sec. II B, Fig. 2(b); App. B):
  * copies every parameter of `from` into the model with d_h = new_dh
  * (new hidden units at the end of each h-block of every matrix, one-hot

@@ -261,6 +261,54 @@ vmc_status rnn_logpsi(const vmc_model *m, const float *params, int64_t nc, const
     return hip_status(launch_forward(a, MODE_LOGPSI, 0, 0, 0, w.fwd_grid, st));
 }
 
+// Local energy from a workspace whose prefix cache (hidden states,
+// conditionals, prefix sums) holds the configurations.
+static vmc_status eloc_from_cache(const Dims &d, const WsMap &w, void *ws, const vmc_ham *H, int64_t ns,
+                                  const uint8_t *configs, double *eloc, hipStream_t st) {
+    const int MT = forward_tile_rows(d.DH);
+    FwdArgs a = base_args(d, ws, w, ns);
+    a.cfg_in = configs;
+    a.hcache = at<float>(ws, w.hcache);
+    a.lpc = at<float>(ws, w.lpc);
+    a.phc = at<float>(ws, w.phc);
+    a.pre = at<double2>(ws, w.pre);
+    hipError_t e = launch_sched(H->kind, d.Lx, d.Ly, ns, configs, at<int>(ws, w.cnt), at<int>(ws, w.list_off),
+                                at<int>(ws, w.list), at<int>(ws, w.tile_start), at<int>(ws, w.tile_counter), MT, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    a.ham_kind = H->kind;
+    a.nbond = bond_count(d.Lx, d.Ly);
+    a.cnt = at<int>(ws, w.cnt);
+    a.tile_start = at<int>(ws, w.tile_start);
+    a.list_off = at<int>(ws, w.list_off);
+    a.list = at<int>(ws, w.list);
+    a.tile_counter = at<int>(ws, w.tile_counter);
+    a.dsuf = at<double2>(ws, w.dsuf);
+    a.NC = w.NC;
+    const bool timed = g_timing.enabled && g_timing.n < ChainTiming::kMax;
+    if (timed && hipEventRecord(g_timing.ev[2 * g_timing.n], st) != hipSuccess) return VMC_EDEVICE;
+    e = launch_forward(a, MODE_CHAIN, 0, 0, 0, w.chain_grid, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    if (timed) {
+        if (hipEventRecord(g_timing.ev[2 * g_timing.n + 1], st) != hipSuccess) return VMC_EDEVICE;
+        g_timing.n++;
+    }
+    return hip_status(launch_assemble(*H, d.Lx, d.Ly, ns, configs, at<float>(ws, w.lpc), at<float>(ws, w.phc),
+                                      at<double2>(ws, w.pre), at<double2>(ws, w.dsuf), w.NC, eloc, st));
+}
+
+// Gradient from a workspace whose hidden states and activations hold the
+// configurations.
+static vmc_status grad_from_cache(const Dims &d, const WsMap &w, void *ws, int64_t ns, const uint8_t *configs,
+                                  const double *eloc, const double *weights, double *grad, double *stats,
+                                  hipStream_t st) {
+    double *st_out = stats ? stats : at<double>(ws, w.stats);
+    return hip_status(launch_grad(d, at<void>(ws, w.BcT), at<void>(ws, w.BgT), at<float>(ws, w.E),
+                                  at<float>(ws, w.Hd), ns, configs, at<float>(ws, w.hcache), at<float>(ws, w.act),
+                                  eloc, weights, st_out, at<float>(ws, w.dcell), at<float>(ws, w.dglu),
+                                  at<float>(ws, w.dhead), at<void>(ws, w.dcol), at<float>(ws, w.part), w.G,
+                                  at<double>(ws, w.gst), grad, st));
+}
+
 vmc_status local_energy(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns,
                         const uint8_t *configs, double *eloc, void *ws, size_t ws_bytes, void *stream) {
     if (!H || (H->kind != VMC_TFIM && H->kind != VMC_HEISENBERG)) return VMC_EINVAL;
@@ -282,33 +330,8 @@ vmc_status local_energy(const vmc_model *m, const float *params, const vmc_ham *
     a.pre = at<double2>(ws, w.pre);
     e = launch_forward(a, MODE_LOGPSI, 1, 1, 0, w.fwd_grid, st);
     if (e != hipSuccess) return VMC_EDEVICE;
-    // 2. connection list and tile schedule
-    e = launch_sched(H->kind, d.Lx, d.Ly, ns, configs, at<int>(ws, w.cnt), at<int>(ws, w.list_off),
-                     at<int>(ws, w.list), at<int>(ws, w.tile_start), at<int>(ws, w.tile_counter), MT, st);
-    if (e != hipSuccess) return VMC_EDEVICE;
-    // 3. all suffix chains of all samples in one persistent launch
-    a.ham_kind = H->kind;
-    a.nbond = bond_count(d.Lx, d.Ly);
-    a.cnt = at<int>(ws, w.cnt);
-    a.tile_start = at<int>(ws, w.tile_start);
-    a.list_off = at<int>(ws, w.list_off);
-    a.list = at<int>(ws, w.list);
-    a.tile_counter = at<int>(ws, w.tile_counter);
-    a.dsuf = at<double2>(ws, w.dsuf);
-    a.NC = w.NC;
-    a.logp = NULL;
-    a.phase = NULL;
-    const bool timed = g_timing.enabled && g_timing.n < ChainTiming::kMax;
-    if (timed && hipEventRecord(g_timing.ev[2 * g_timing.n], st) != hipSuccess) return VMC_EDEVICE;
-    e = launch_forward(a, MODE_CHAIN, 0, 0, 0, w.chain_grid, st);
-    if (e != hipSuccess) return VMC_EDEVICE;
-    if (timed) {
-        if (hipEventRecord(g_timing.ev[2 * g_timing.n + 1], st) != hipSuccess) return VMC_EDEVICE;
-        g_timing.n++;
-    }
-    // 4. assembly
-    return hip_status(launch_assemble(*H, d.Lx, d.Ly, ns, configs, at<float>(ws, w.lpc), at<float>(ws, w.phc),
-                                      at<double2>(ws, w.pre), at<double2>(ws, w.dsuf), w.NC, eloc, st));
+    // 2. all connected configurations of all samples: schedule, one persistent launch, assembly
+    return eloc_from_cache(d, w, ws, H, ns, configs, eloc, st);
 }
 
 vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const uint8_t *configs,
@@ -328,12 +351,44 @@ vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const u
     a.act = at<float>(ws, w.act);
     e = launch_forward(a, MODE_LOGPSI, 1, 0, 1, w.fwd_grid, st);
     if (e != hipSuccess) return VMC_EDEVICE;
-    double *st_out = stats ? stats : at<double>(ws, w.stats);
-    return hip_status(launch_grad(d, at<void>(ws, w.BcT), at<void>(ws, w.BgT), at<float>(ws, w.E),
-                                  at<float>(ws, w.Hd), ns, configs, at<float>(ws, w.hcache), at<float>(ws, w.act),
-                                  eloc, weights, st_out, at<float>(ws, w.dcell), at<float>(ws, w.dglu),
-                                  at<float>(ws, w.dhead), at<void>(ws, w.dcol), at<float>(ws, w.part), w.G,
-                                  at<double>(ws, w.gst), grad, st));
+    return grad_from_cache(d, w, ws, ns, configs, eloc, weights, grad, stats, st);
+}
+
+vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns, uint64_t seed,
+                    uint64_t counter, const float *uniforms, uint8_t *configs, float *logp, float *phase,
+                    double *eloc, double *grad, double *stats, void *ws, size_t ws_bytes, void *stream) {
+    if (!H || (H->kind != VMC_TFIM && H->kind != VMC_HEISENBERG)) return VMC_EINVAL;
+    vmc_status s = check_common(m, params, ns, ws, ws_bytes, H, NULL);
+    if (s != VMC_OK) return s;
+    if (!configs || !logp || !eloc || !grad) return VMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Dims d = make_dims(m);
+    WsMap w = ws_map(d, H, ns);
+    hipError_t e = stage(d, params, ws, w, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    // sampling keeps everything the later phases read
+    FwdArgs a = base_args(d, ws, w, ns);
+    a.uniforms = uniforms;
+    a.seed = seed;
+    a.counter = counter;
+    a.cfg_out = configs;
+    a.cfg_in = configs;
+    a.logp = logp;
+    a.phase = d.cplx ? phase : NULL;
+    a.hcache = at<float>(ws, w.hcache);
+    a.lpc = at<float>(ws, w.lpc);
+    a.phc = at<float>(ws, w.phc);
+    a.pre = at<double2>(ws, w.pre);
+    a.act = at<float>(ws, w.act);
+    if (phase && !d.cplx) {
+        e = launch_fill(phase, ns, 0.0f, st);
+        if (e != hipSuccess) return VMC_EDEVICE;
+    }
+    e = launch_forward(a, MODE_SAMPLE, 1, 1, 1, w.fwd_grid, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    s = eloc_from_cache(d, w, ws, H, ns, configs, eloc, st);
+    if (s != VMC_OK) return s;
+    return grad_from_cache(d, w, ws, ns, configs, eloc, NULL, grad, stats, st);
 }
 
 vmc_status grow_hidden(const vmc_model *from, const float *p_from, int32_t new_dh, uint64_t seed, double noise_std,

@@ -14,7 +14,7 @@
 
 namespace vmc {
 
-constexpr int DW_TILE = 64;     // output tile of the weight-gradient contraction
+constexpr int DW_TILE = 128;    // output tile of the weight-gradient contraction
 constexpr int DW_ROWS = 4096;   // rows per FP32 partial (summed in FP64 afterwards)
 
 // ------------------------------------------------------------- statistics
@@ -354,92 +354,142 @@ struct DwArgs {
     int seg;             // 0 cell, 1 GLU, 2 heads
     int64_t ns, R;       // R = N * ns rows, row = q * ns + s
     const float *D;      // [R][MD] deltas
-    int MD, Mp, Kp;      // delta row width, padded output dims
+    int MD, KX, Mp, Kp;  // delta row width, input row width, padded output dims
     const float *hcache, *act;
     const uint8_t *cfg;
     float *part;         // [G][Mp][Kp]
 };
 
-// Input row of the contraction for segment `seg` at row (q, s), column k:
+// Input row of the contraction for segment `seg` at row (q, s):
 //  cell 1D: [h_{q-1} | 1 | onehot(sigma_{q-1})]
 //  cell 2D: [h_hz | h_vt | 1 | onehot_hz | onehot_vt]
 //  GLU:     [h_q | 1];   heads: [g_q | 1]
-__device__ inline float dw_input(const DwArgs &a, int q, int s, int k) {
+// Described per row by up to two contiguous hidden sources (element offsets
+// into hcache or act, -1 = absent) and up to five extra values.
+struct DwRow {
+    int64_t src0, src1;
+    float ex[5];
+};
+
+__device__ inline DwRow dw_row(const DwArgs &a, int q, int s) {
     const int DH = a.d.DH, Lx = a.d.Lx, N = a.d.N;
     const int64_t ns = a.ns;
+    DwRow r;
+    r.src0 = r.src1 = -1;
+    for (int i = 0; i < 5; i++) r.ex[i] = 0.f;
+    r.ex[0] = 1.f;
     if (a.seg == 1) {
-        if (k < DH) return a.hcache[((int64_t)q * ns + s) * DH + k];
-        return k == DH ? 1.f : 0.f;
+        r.src0 = ((int64_t)q * ns + s) * DH;
+        return r;
     }
     if (a.seg == 2) {
-        if (k < DH) {
-            const int AW = act_width(a.d.dims, DH);
-            return a.act[((int64_t)q * ns + s) * AW + (nact_per_unit(a.d.dims) + 2) * DH + k];
-        }
-        return k == DH ? 1.f : 0.f;
+        r.src0 = ((int64_t)q * ns + s) * act_width(a.d.dims, DH) + (nact_per_unit(a.d.dims) + 2) * DH;
+        return r;
     }
     const bool has_hz = (q % Lx) != 0;
     if (a.d.dims == 1) {
-        if (k < DH) return has_hz ? a.hcache[((int64_t)(q - 1) * ns + s) * DH + k] : 0.f;
-        if (k == DH) return 1.f;
-        if (k <= DH + 2) return (has_hz && a.cfg[(int64_t)s * N + (q - 1)] == k - DH - 1) ? 1.f : 0.f;
-        return 0.f;
+        if (has_hz) {
+            r.src0 = ((int64_t)(q - 1) * ns + s) * DH;
+            const int x = a.cfg[(int64_t)s * N + (q - 1)];
+            r.ex[1 + x] = 1.f;
+        }
+        return r;
     }
     const int site = order_site(q, Lx);
-    const int jrow = q / Lx;
-    const bool has_vt = jrow > 0;
-    if (k < DH) return has_hz ? a.hcache[((int64_t)(q - 1) * ns + s) * DH + k] : 0.f;
-    if (k < 2 * DH) {
-        if (!has_vt) return 0.f;
-        const int pv = site_pos(site - Lx, Lx);
-        return a.hcache[((int64_t)pv * ns + s) * DH + (k - DH)];
+    if (has_hz) {
+        r.src0 = ((int64_t)(q - 1) * ns + s) * DH;
+        r.ex[1 + a.cfg[(int64_t)s * N + order_site(q - 1, Lx)]] = 1.f;
     }
-    if (k == 2 * DH) return 1.f;
-    if (k <= 2 * DH + 2)
-        return (has_hz && a.cfg[(int64_t)s * N + order_site(q - 1, Lx)] == k - 2 * DH - 1) ? 1.f : 0.f;
-    if (k <= 2 * DH + 4) return (has_vt && a.cfg[(int64_t)s * N + site - Lx] == k - 2 * DH - 3) ? 1.f : 0.f;
-    return 0.f;
+    if (q >= Lx) {
+        r.src1 = ((int64_t)site_pos(site - Lx, Lx) * ns + s) * DH;
+        r.ex[3 + a.cfg[(int64_t)s * N + site - Lx]] = 1.f;
+    }
+    return r;
 }
 
-// dW[m][k] partial over DW_ROWS rows: FP32 MFMA 16x16x4, 64x64 output tile,
-// 4 waves as 2x2 of 32x32.  Grid (m tiles, k tiles, row chunks).
+// dW[m][k] partial over DW_ROWS rows: FP32 MFMA 16x16x4 on a 128x128 output
+// tile, 4 waves as 2x2 of 64x64.  Grid (m tiles, k tiles, row chunks).  The
+// deltas and the inputs of 16 rows at a time are staged in LDS with 16-byte
+// loads; each hidden input row is one contiguous source.
 __global__ __launch_bounds__(256) void dw_kernel(DwArgs a) {
-    constexpr int RS = 32, LD = DW_TILE + 4;
-    __shared__ float sD[RS][LD], sX[RS][LD];
+    constexpr int RS = 16, T = DW_TILE, LD = T + 4;
+    __shared__ __align__(16) float sD[RS][LD];
+    __shared__ __align__(16) float sX[RS][LD];
+    __shared__ DwRow sR[RS];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int m0 = blockIdx.x * DW_TILE, k0 = blockIdx.y * DW_TILE;
+    const int m0 = blockIdx.x * T, k0 = blockIdx.y * T;
     const int64_t r0 = (int64_t)blockIdx.z * DW_ROWS;
     const int64_t r1 = min(r0 + DW_ROWS, a.R);
-    const int wm = (w >> 1) * 32, wk = (w & 1) * 32;
-    f32x4_t acc[2][2];
+    const int wm = (w >> 1) * 64, wk = (w & 1) * 64;
+    const int DH = a.d.DH;
+    const int nhid = (a.seg == 0 && a.d.dims == 2) ? 2 * DH : DH;  // hidden columns of the input
+    const float *xsrc = a.seg == 2 ? a.act : a.hcache;
+    f32x4_t acc[4][4];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < 4; j++) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    // blocks of this wave that hold real output
+    const int mlim = a.MD - (m0 + wm), klim = a.KX - (k0 + wk);
     for (int64_t rb = r0; rb < r1; rb += RS) {
-        for (int e = tid; e < RS * DW_TILE; e += 256) {
-            const int rr = e / DW_TILE, c = e % DW_TILE;
-            const int64_t row = rb + rr;
-            float dv = 0.f, xv = 0.f;
+        if (tid < RS) {
+            const int64_t row = rb + tid;
+            DwRow r;
             if (row < r1) {
-                const int q = (int)(row / a.ns), s = (int)(row % a.ns);
-                const int m = m0 + c, k = k0 + c;
-                if (m < a.MD) dv = a.D[row * a.MD + m];
-                xv = dw_input(a, q, s, k);
+                r = dw_row(a, (int)(row / a.ns), (int)(row % a.ns));
+            } else {
+                r.src0 = r.src1 = -1;
+                for (int i = 0; i < 5; i++) r.ex[i] = 0.f;
             }
-            sD[rr][c] = dv;
-            sX[rr][c] = xv;
+            sR[tid] = r;
+        }
+        __syncthreads();
+        for (int e = tid; e < RS * (T / 4); e += 256) {
+            const int rr = e / (T / 4), c = (e % (T / 4)) * 4;
+            const int64_t row = rb + rr;
+            float4 dv = make_float4(0.f, 0.f, 0.f, 0.f), xv = dv;
+            if (row < r1) {
+                const int m = m0 + c;
+                if (m + 3 < a.MD) dv = *(const float4 *)&a.D[row * a.MD + m];
+                else if (m < a.MD) {
+                    dv.x = a.D[row * a.MD + m];
+                    if (m + 1 < a.MD) dv.y = a.D[row * a.MD + m + 1];
+                    if (m + 2 < a.MD) dv.z = a.D[row * a.MD + m + 2];
+                }
+                const int k = k0 + c;
+                const DwRow &R = sR[rr];
+                if (k < nhid) {
+                    const int blk = k >= DH, kk = k - blk * DH;
+                    const int64_t src = blk ? R.src1 : R.src0;
+                    if (src >= 0) xv = *(const float4 *)&xsrc[src + kk];
+                } else {
+                    float t[4];
+#pragma unroll
+                    for (int x = 0; x < 4; x++) {
+                        const int ke = k + x - nhid;
+                        t[x] = (ke < 5) ? R.ex[ke] : 0.f;
+                    }
+                    xv = make_float4(t[0], t[1], t[2], t[3]);
+                }
+            }
+            *(float4 *)&sD[rr][c] = dv;
+            *(float4 *)&sX[rr][c] = xv;
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < RS; kk += 4) {
+            float av[4], bv[4];
 #pragma unroll
-            for (int i = 0; i < 2; i++) {
-                const float av = sD[kk + (lane >> 4)][wm + i * 16 + (lane & 15)];
+            for (int i = 0; i < 4; i++) av[i] = sD[kk + (lane >> 4)][wm + i * 16 + (lane & 15)];
 #pragma unroll
-                for (int j = 0; j < 2; j++) {
-                    const float bv = sX[kk + (lane >> 4)][wk + j * 16 + (lane & 15)];
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i][j], 0, 0, 0);
+            for (int j = 0; j < 4; j++) bv[j] = sX[kk + (lane >> 4)][wk + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                if (i * 16 >= mlim) continue;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if (j * 16 >= klim) continue;
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
                 }
             }
         }
@@ -447,9 +497,9 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs a) {
     }
     float *out = a.part + (int64_t)blockIdx.z * a.Mp * a.Kp;
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int j = 0; j < 4; j++)
 #pragma unroll
             for (int ii = 0; ii < 4; ii++) {
                 const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + ii;
@@ -536,21 +586,22 @@ __global__ void fill_f64(double *p, int64_t n, double v) {
 // ------------------------------------------------------------------ host
 
 struct SegDims {
-    int MD, Mp, Kp;
+    int MD, KX, Mp, Kp;
 };
 
 static SegDims seg_dims(const Dims &d, int seg) {
     SegDims s;
     if (seg == 0) {
         s.MD = d.dims == 1 ? 4 * d.DH : 3 * d.DH;
-        s.Kp = cround(d.dims == 1 ? d.DH + 3 : 2 * d.DH + 5, DW_TILE);
+        s.KX = d.dims == 1 ? d.DH + 3 : 2 * d.DH + 5;
     } else if (seg == 1) {
         s.MD = 2 * d.DH;
-        s.Kp = cround(d.DH + 1, DW_TILE);
+        s.KX = d.DH + 1;
     } else {
         s.MD = 4;
-        s.Kp = cround(d.DH + 1, DW_TILE);
+        s.KX = d.DH + 1;
     }
+    s.Kp = cround(s.KX, DW_TILE);
     s.Mp = cround(s.MD, DW_TILE);
     return s;
 }
@@ -637,6 +688,7 @@ hipError_t launch_grad(const Dims &d, const void *BcT, const void *BgT, const fl
         a.R = (int64_t)d.N * ns;
         a.D = seg == 0 ? dcell : seg == 1 ? dglu : dhead;
         a.MD = sd.MD;
+        a.KX = sd.KX;
         a.Mp = sd.Mp;
         a.Kp = sd.Kp;
         a.hcache = hcache;

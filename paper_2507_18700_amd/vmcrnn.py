@@ -17,7 +17,7 @@ VMC_FP32, VMC_BF16 = 0, 1
 VMC_TFIM, VMC_HEISENBERG = 0, 1
 
 EXPORTS = ("vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "local_energy",
-           "vmc_grad", "grow_hidden", "vmc_chain_timing", "vmc_chain_time", "vmc_status_str")
+           "vmc_grad", "vmc_step", "grow_hidden", "vmc_chain_timing", "vmc_chain_time", "vmc_status_str")
 
 
 class VmcError(RuntimeError):
@@ -74,6 +74,8 @@ def lib():
         L.local_energy.argtypes = [P(Model), vp, P(Ham), i64, vp, vp, vp, sz, vp]
         L.vmc_grad.restype = ctypes.c_int
         L.vmc_grad.argtypes = [P(Model), vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.vmc_step.restype = ctypes.c_int
+        L.vmc_step.argtypes = [P(Model), vp, P(Ham), i64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.grow_hidden.restype = ctypes.c_int
         L.grow_hidden.argtypes = [P(Model), vp, ctypes.c_int32, u64, d, vp, vp, vp, vp, vp, vp]
         L.vmc_chain_timing.restype = ctypes.c_int
@@ -205,6 +207,29 @@ def vmc_grad(m, params, configs, eloc, weights=None, ws=None, out=None):
     _check(lib().vmc_grad(ctypes.byref(m), _ptr(params), ns, _ptr(configs), _ptr(eloc), _ptr(weights), _ptr(g),
                           _ptr(st), _ptr(buf), nb, _stream()))
     return g, st
+
+
+def vmc_step(m, params, H, ns, seed=0, counter=0, uniforms=None, ws=None, out=None):
+    """One VMC step (sample, local energy, gradient with w = 1/ns) sharing one
+    forward pass; returns (configs, logp, phase, eloc, grad, stats)."""
+    _dev(params, torch.float32, "params")
+    dev = params.device
+    if uniforms is not None:
+        _dev(uniforms, torch.float32, "uniforms")
+        if uniforms.shape != (ns, m.N):
+            raise ValueError("uniforms must have shape [ns, N]")
+    if out is None:
+        out = (torch.empty((ns, m.N), dtype=torch.uint8, device=dev),
+               torch.empty(ns, dtype=torch.float32, device=dev),
+               torch.empty(ns, dtype=torch.float32, device=dev),
+               torch.empty((ns, 2), dtype=torch.float64, device=dev),
+               torch.empty(param_count(m), dtype=torch.float64, device=dev),
+               torch.empty(4, dtype=torch.float64, device=dev))
+    cfg, lp, ph, e, g, st = out
+    buf, nb = _ws(ws, m, H, ns)
+    _check(lib().vmc_step(ctypes.byref(m), _ptr(params), ctypes.byref(H), ns, seed, counter, _ptr(uniforms),
+                          _ptr(cfg), _ptr(lp), _ptr(ph), _ptr(e), _ptr(g), _ptr(st), _ptr(buf), nb, _stream()))
+    return cfg, lp, ph, e, g, st
 
 
 def grow_hidden(m, params, new_dh, seed, noise_std, m_mom=None, v_mom=None):

@@ -32,7 +32,7 @@ def lib():
 def test_exports_every_declared_symbol(lib):
     names = declared()
     assert set(names) == {"vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "local_energy",
-                          "vmc_grad", "grow_hidden", "vmc_chain_timing", "vmc_chain_time", "vmc_status_str"}
+                          "vmc_grad", "vmc_step", "grow_hidden", "vmc_chain_timing", "vmc_chain_time", "vmc_status_str"}
     L = ctypes.CDLL(LIB)
     for n in names:
         assert hasattr(L, n), n
