@@ -63,10 +63,12 @@ struct BF16 {
 };
 
 // -------------------------------------------------------------- activations
-// Logistic function and tanh from the hardware exp2 and reciprocal; tanh via
-// 2*sigmoid(2x) - 1, whose absolute error stays at float rounding level.
-__device__ inline float sigmoidf_(float x) { return __frcp_rn(1.0f + __expf(-x)); }
-__device__ inline float tanhf_(float x) { return 2.0f * __frcp_rn(1.0f + __expf(-2.0f * x)) - 1.0f; }
+// Logistic function and tanh from the hardware exp2 (v_exp_f32) and
+// reciprocal (v_rcp_f32, 1 ulp); tanh via 2*sigmoid(2x) - 1, whose absolute
+// error stays at float rounding level.
+__device__ inline float rcpf_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float sigmoidf_(float x) { return rcpf_(1.0f + __expf(-x)); }
+__device__ inline float tanhf_(float x) { return 2.0f * rcpf_(1.0f + __expf(-2.0f * x)) - 1.0f; }
 __device__ inline float softsignf_(float x) { return x / (1.0f + fabsf(x)); }
 
 // ------------------------------------------------------------------- Philox
@@ -100,16 +102,14 @@ __host__ __device__ inline int site_pos(int site, int Lx) {
 
 // --------------------------------------------------------- staged weights
 // Device copy of the parameters in MFMA-ready form, padded to DH (a multiple
-// of 16 >= d_h) with zeros, built by the staging kernel for every call.
-//   Bc  [3*DH][KP]  cell weights on the hidden input, row n = gate*DH + unit,
-//                   1D gates (u, r, m) = (W_g, W_r, W_h) on h_{n-1};
-//                   2D gates (c, u, v) = (W, W_g, U) on [h_hz | h_vt], the
-//                   vertical block starting at column DH.
-//   BcT [KP][3*DH]  its transpose (backward).
-//   Bg  [2*DH][DH]  GLU (W_1 rows, then W_2 rows);  BgT [DH][2*DH].
+// of 16 >= d_h) with zeros, built by the staging kernel for every call (the
+// exact layouts are documented at stage_weights):
+//   Bc  cell weights, row n = gate*DH + unit; 1D gates (u, r, m) = (W_g, W_r,
+//       W_h) on h_{n-1}; 2D gates (c, u, v) = (W, W_g, U) on [h_hz | h_vt];
+//       followed by the one-hot (indicator) columns;  BcT its hidden part
+//       transposed (backward);  Bg / BgT the GLU (W_1 rows, then W_2 rows).
 //   E   [ESLOTS][DH] FP32 epilogue table, see the slot names below.
 //   Hd  [4][DH]     heads U_a (rows 0,1) and U_p (rows 2,3); hc[4]: c_a, c_p.
-// KP = K rounded up to the contraction step, K = DH (1D) or 2*DH (2D).
 enum {
     // 1D
     E1_BG = 0, E1_XG0, E1_XG1, E1_BR, E1_XR0, E1_XR1, E1_BH, E1_BIN, E1_XIN0, E1_XIN1,

@@ -46,11 +46,19 @@ struct Eng {
 };
 
 // Sum over the 16 lanes of a DPP row; every lane of the row gets the sum.
+// Each stage is one v_add_f32 with a DPP source (quad swaps, then the half-
+// row and row mirrors).  A DPP read of a VGPR written by the previous VALU
+// instruction needs two wait states, hence the s_nop before each stage.
 __device__ inline float row16_sum(float v) {
-    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x140, 0xF, 0xF, false));
+    float t;
+    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
+                 : "=&v"(t) : "v"(v));
+    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
+                 : "=&v"(v) : "v"(t));
+    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_half_mirror row_mask:0xf bank_mask:0xf"
+                 : "=&v"(t) : "v"(v));
+    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_mirror row_mask:0xf bank_mask:0xf"
+                 : "=&v"(v) : "v"(t));
     return v;
 }
 
@@ -61,9 +69,11 @@ __device__ inline float cvt<F32>(float x) { return x; }
 template <>
 __device__ inline uint16_t cvt<BF16>(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 
-template <class P, int DIMS, int DH, int NW, int REGW>
-__global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int store_h, int store_lpc,
-                                                      int store_act) {
+template <class P, int DIMS, int DH, int NW, int REGW, int STORE>
+__global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int store_h_, int store_lpc_,
+                                                      int store_act_) {
+    // cache writes exist only in the STORE variant (the chain kernel has none)
+    const int store_h = STORE && store_h_, store_lpc = STORE && store_lpc_, store_act = STORE && store_act_;
     typedef Eng<P, DIMS, DH, NW> C;
     typedef typename P::store_t T;
     constexpr int MT = C::MT, RB = C::RB, UB = C::UB, KS = C::KS, VEC = P::VEC;
@@ -294,47 +304,28 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             }
             __syncthreads();
 
-            // 2. cell contraction on MFMA
-            f32x4_t acc[RB][3 * UB];
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                for (int c = 0; c < 3 * UB; c++) acc[rb][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int ks = 0; ks < NKS; ks++) {
-                const int blk = ks / NKB;  // 0 hz, 1 vt (2D), last = indicators
+            // 2.+3. cell contraction on MFMA and the gate algebra (App. A); the
+            // new h goes to sH[cb].  With register-resident weights one row
+            // block at a time, so that the epilogue of one block runs under
+            // the MFMAs of the next; with streamed weights all row blocks per
+            // weight fragment (each fragment loaded once per step).
+            float hv[RB][UB][4];
+            auto a_frag = [&](int rb, int ks) -> uint4 {
+                const int blk = ks / NKB;
                 const bool is_x = ks == NKS - 1;
-                if (!is_x && blk == 0 && !has_hz) continue;
-                if (!is_x && blk == 1 && !has_vt) continue;
                 const T *Aop = is_x ? sX : (blk == 0 || vt_prev) ? sH[pb] : sV;
                 const int ald = is_x ? X_LD : H_LD;
                 const int kc = is_x ? 0 : (ks % NKB) * KS;
-                uint4 af[RB];
-#pragma unroll
-                for (int rb = 0; rb < RB; rb++) {
-                    const int row = wr * C::RW + rb * 16 + l16;
-                    af[rb] = *(const uint4 *)&Aop[row * ald + kc + VEC * lq];
-                }
-#pragma unroll
-                for (int g = 0; g < 3; g++)
-#pragma unroll
-                    for (int ub = 0; ub < UB; ub++) {
-                        uint4 bf;
-                        if (REGW) {
-                            bf = wreg[REGW ? g : 0][REGW ? ks : 0][REGW ? ub : 0];
-                        } else {
-                            const int n = g * DH + wu * C::UW + ub * 16 + l16;
-                            bf = *(const uint4 *)&Bc[(int64_t)n * KPX + ks * KS + VEC * lq];
-                        }
-#pragma unroll
-                        for (int rb = 0; rb < RB; rb++) P::mma(acc[rb][g * UB + ub], af[rb], bf);
-                    }
-            }
-
-            // 3. gate algebra (App. A); the new h goes to sH[cb]
-            float hv[RB][UB][4];
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++)
+                const int arow = wr * C::RW + rb * 16 + l16;
+                return *(const uint4 *)&Aop[arow * ald + kc + VEC * lq];
+            };
+            auto ks_active = [&](int ks) -> bool {
+                const int blk = ks / NKB;
+                if (ks == NKS - 1) return true;
+                if (blk == 0) return has_hz;
+                return has_vt;
+            };
+            auto epilogue = [&](int rb, const f32x4_t *acc) {
 #pragma unroll
                 for (int ii = 0; ii < 4; ii++) {
                     const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
@@ -344,7 +335,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 #pragma unroll
                     for (int ub = 0; ub < UB; ub++) {
                         const int u = wu * C::UW + ub * 16 + l16;
-                        const float g0 = acc[rb][ub][ii], g1 = acc[rb][UB + ub][ii], g2 = acc[rb][2 * UB + ub][ii];
+                        const float g0 = acc[ub][ii], g1 = acc[UB + ub][ii], g2 = acc[2 * UB + ub][ii];
                         float h, s0, s1, s2, s3 = 0.f;
                         if (DIMS == 1) {
                             const float uu = sigmoidf_(g0 + bias0[ub]);
@@ -363,7 +354,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                             s0 = c; s1 = uu; s2 = g2;
                         }
                         hv[rb][ub][ii] = h;
-                        sH[cb][r * H_LD + u] = cvt<P>(h);
+                        if (DIMS == 2) sH[cb][r * H_LD + u] = cvt<P>(h);
                         if (s >= 0) {
                             if (store_h) a.hcache[((int64_t)q * ns_c + s) * DH + u] = h;
                             if (store_act) {
@@ -376,6 +367,62 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                         }
                     }
                 }
+            };
+            if (REGW) {
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++) {
+                    f32x4_t acc[3 * UB];
+#pragma unroll
+                    for (int c = 0; c < 3 * UB; c++) acc[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < NKS; ks++) {
+                        if (!ks_active(ks)) continue;
+                        const uint4 af = a_frag(rb, ks);
+#pragma unroll
+                        for (int g = 0; g < 3; g++)
+#pragma unroll
+                            for (int ub = 0; ub < UB; ub++)
+                                P::mma(acc[g * UB + ub], af, wreg[REGW ? g : 0][REGW ? ks : 0][REGW ? ub : 0]);
+                    }
+                    epilogue(rb, acc);
+                }
+            } else {
+                f32x4_t acc[RB][3 * UB];
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                    for (int c = 0; c < 3 * UB; c++) acc[rb][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < NKS; ks++) {
+                    if (!ks_active(ks)) continue;
+                    uint4 af[RB];
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++) af[rb] = a_frag(rb, ks);
+#pragma unroll
+                    for (int g = 0; g < 3; g++)
+#pragma unroll
+                        for (int ub = 0; ub < UB; ub++) {
+                            const int n = g * DH + wu * C::UW + ub * 16 + l16;
+                            const uint4 bf = *(const uint4 *)&Bc[(int64_t)n * KPX + ks * KS + VEC * lq];
+#pragma unroll
+                            for (int rb = 0; rb < RB; rb++) P::mma(acc[rb][g * UB + ub], af[rb], bf);
+                        }
+                }
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++) epilogue(rb, acc[rb]);
+            }
+            if (DIMS == 1) {
+                // in 1D the operand buffer of this step is sH[pb]; writing
+                // sH[cb] could not race, but keep one writer pattern for both
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                    for (int ii = 0; ii < 4; ii++)
+#pragma unroll
+                        for (int ub = 0; ub < UB; ub++)
+                            sH[cb][(wr * C::RW + rb * 16 + 4 * lq + ii) * H_LD + wu * C::UW + ub * 16 + l16] =
+                                cvt<P>(hv[rb][ub][ii]);
+            }
             __syncthreads();
 
             // the column buffer keeps h for the vertical input of the next row
@@ -387,14 +434,82 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             }
 
             // 4. GLU (MFMA) and heads (FP32)
-            float part[RB][4][4];
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++)
+            auto glu_epilogue = [&](int rb, const f32x4_t *acc2) {
+                float part[4][4];
 #pragma unroll
                 for (int ii = 0; ii < 4; ii++)
 #pragma unroll
-                    for (int o = 0; o < 4; o++) part[rb][ii][o] = 0.f;
-            if (glu) {
+                    for (int o = 0; o < 4; o++) part[ii][o] = 0.f;
+#pragma unroll
+                for (int ii = 0; ii < 4; ii++) {
+                    const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
+                    const int s = sRow[r];
+#pragma unroll
+                    for (int ub = 0; ub < UB; ub++) {
+                        const int u = wu * C::UW + ub * 16 + l16;
+                        float g;
+                        if (glu) {
+                            const float a1 = acc2[ub][ii] + gb1[ub];
+                            const float a2 = acc2[UB + ub][ii] + gb2[ub];
+                            g = a1 * sigmoidf_(a2);
+                            if (store_act && s >= 0) {
+                                float *ar = a.act + ((int64_t)q * ns_c + s) * AW + NA * DH;
+                                ar[u] = a1;
+                                ar[DH + u] = a2;
+                                ar[2 * DH + u] = g;
+                            }
+                        } else {
+                            g = hv[rb][ub][ii];
+                            if (store_act && s >= 0) a.act[((int64_t)q * ns_c + s) * AW + (NA + 2) * DH + u] = g;
+                        }
+                        part[ii][0] += hw[0][ub] * g;
+                        part[ii][1] += hw[1][ub] * g;
+                        if (cplx) {
+                            part[ii][2] += hw[2][ub] * g;
+                            part[ii][3] += hw[3][ub] * g;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int ii = 0; ii < 4; ii++) {
+                    const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
+                    const float v0 = row16_sum(part[ii][0]);
+                    const float v1 = row16_sum(part[ii][1]);
+                    float v2 = 0.f, v3 = 0.f;
+                    if (cplx) {
+                        v2 = row16_sum(part[ii][2]);
+                        v3 = row16_sum(part[ii][3]);
+                    }
+                    if (l16 == 0) *(float4 *)&sLog[wu][r][0] = make_float4(v0, v1, v2, v3);
+                }
+            };
+            auto glu_frag = [&](int rb, int kk) -> uint4 {
+                const int arow = wr * C::RW + rb * 16 + l16;
+                return *(const uint4 *)&sH[cb][arow * H_LD + kk + VEC * lq];
+            };
+            if (!glu) {
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++) glu_epilogue(rb, nullptr);
+            } else if (REGW) {
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++) {
+                    f32x4_t acc2[2 * UB];
+#pragma unroll
+                    for (int c = 0; c < 2 * UB; c++) acc2[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kk = 0; kk < KHB; kk += KS) {
+                        const uint4 af = glu_frag(rb, kk);
+#pragma unroll
+                        for (int g = 0; g < 2; g++)
+#pragma unroll
+                            for (int ub = 0; ub < UB; ub++) {
+                                const int n = g * DH + wu * C::UW + ub * 16 + l16;
+                                P::mma(acc2[g * UB + ub], af, *(const uint4 *)&sG[n * GLD + kk + VEC * lq]);
+                            }
+                    }
+                    glu_epilogue(rb, acc2);
+                }
+            } else {
                 f32x4_t acc2[RB][2 * UB];
 #pragma unroll
                 for (int rb = 0; rb < RB; rb++)
@@ -404,84 +519,20 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 for (int kk = 0; kk < KHB; kk += KS) {
                     uint4 af[RB];
 #pragma unroll
-                    for (int rb = 0; rb < RB; rb++) {
-                        const int row = wr * C::RW + rb * 16 + l16;
-                        af[rb] = *(const uint4 *)&sH[cb][row * H_LD + kk + VEC * lq];
-                    }
+                    for (int rb = 0; rb < RB; rb++) af[rb] = glu_frag(rb, kk);
 #pragma unroll
                     for (int g = 0; g < 2; g++)
 #pragma unroll
                         for (int ub = 0; ub < UB; ub++) {
                             const int n = g * DH + wu * C::UW + ub * 16 + l16;
-                            uint4 bf;
-                            if (REGW) bf = *(const uint4 *)&sG[n * GLD + kk + VEC * lq];
-                            else bf = *(const uint4 *)&Bg[(int64_t)n * KHB + kk + VEC * lq];
+                            const uint4 bf = *(const uint4 *)&Bg[(int64_t)n * KHB + kk + VEC * lq];
 #pragma unroll
                             for (int rb = 0; rb < RB; rb++) P::mma(acc2[rb][g * UB + ub], af[rb], bf);
                         }
                 }
 #pragma unroll
-                for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                    for (int ii = 0; ii < 4; ii++) {
-                        const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
-                        const int s = sRow[r];
-#pragma unroll
-                        for (int ub = 0; ub < UB; ub++) {
-                            const int u = wu * C::UW + ub * 16 + l16;
-                            const float a1 = acc2[rb][ub][ii] + gb1[ub];
-                            const float a2 = acc2[rb][UB + ub][ii] + gb2[ub];
-                            const float g = a1 * sigmoidf_(a2);
-                            if (store_act && s >= 0) {
-                                float *ar = a.act + ((int64_t)q * ns_c + s) * AW + NA * DH;
-                                ar[u] = a1;
-                                ar[DH + u] = a2;
-                                ar[2 * DH + u] = g;
-                            }
-                            part[rb][ii][0] += hw[0][ub] * g;
-                            part[rb][ii][1] += hw[1][ub] * g;
-                            part[rb][ii][2] += hw[2][ub] * g;
-                            part[rb][ii][3] += hw[3][ub] * g;
-                        }
-                    }
-            } else {
-#pragma unroll
-                for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                    for (int ii = 0; ii < 4; ii++) {
-                        const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
-                        const int s = sRow[r];
-#pragma unroll
-                        for (int ub = 0; ub < UB; ub++) {
-                            const int u = wu * C::UW + ub * 16 + l16;
-                            const float g = hv[rb][ub][ii];
-                            if (store_act && s >= 0) a.act[((int64_t)q * ns_c + s) * AW + (NA + 2) * DH + u] = g;
-                            part[rb][ii][0] += hw[0][ub] * g;
-                            part[rb][ii][1] += hw[1][ub] * g;
-                            part[rb][ii][2] += hw[2][ub] * g;
-                            part[rb][ii][3] += hw[3][ub] * g;
-                        }
-                    }
+                for (int rb = 0; rb < RB; rb++) glu_epilogue(rb, acc2[rb]);
             }
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                for (int ii = 0; ii < 4; ii++) {
-                    const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
-                    const float v0 = row16_sum(part[rb][ii][0]);
-                    const float v1 = row16_sum(part[rb][ii][1]);
-                    float v2 = 0.f, v3 = 0.f;
-                    if (cplx) {
-                        v2 = row16_sum(part[rb][ii][2]);
-                        v3 = row16_sum(part[rb][ii][3]);
-                    }
-                    if (l16 == 0) {
-                        sLog[wu][r][0] = v0;
-                        sLog[wu][r][1] = v1;
-                        sLog[wu][r][2] = v2;
-                        sLog[wu][r][3] = v3;
-                    }
-                }
             __syncthreads();
 
             // 5. per-row finalisation
@@ -556,15 +607,22 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 
 // ------------------------------------------------------------ launchers
 
-template <class P, int DIMS, int DH, int NW, int REGW>
-static hipError_t launch_engine_t(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
+template <class P, int DIMS, int DH, int NW, int REGW, int STORE>
+static hipError_t launch_engine_s(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
     typedef Eng<P, DIMS, DH, NW> C;
     size_t dyn = ((size_t)C::MT * a.d.N + 15) / 16 * 16;
-    hipError_t e = hipFuncSetAttribute((const void *)rnn_engine<P, DIMS, DH, NW, REGW>,
+    hipError_t e = hipFuncSetAttribute((const void *)rnn_engine<P, DIMS, DH, NW, REGW, STORE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rnn_engine<P, DIMS, DH, NW, REGW>), dim3(grid), dim3(NW * 64), dyn, st, a, mode, sh, sl, sa);
+    hipLaunchKernelGGL((rnn_engine<P, DIMS, DH, NW, REGW, STORE>), dim3(grid), dim3(NW * 64), dyn, st, a, mode, sh,
+                       sl, sa);
     return hipGetLastError();
+}
+
+template <class P, int DIMS, int DH, int NW, int REGW>
+static hipError_t launch_engine_t(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
+    if (sh || sl || sa) return launch_engine_s<P, DIMS, DH, NW, REGW, 1>(a, mode, sh, sl, sa, grid, st);
+    return launch_engine_s<P, DIMS, DH, NW, REGW, 0>(a, mode, sh, sl, sa, grid, st);
 }
 
 // Variant per precision and width: bfloat16 up to d_h = 128 keeps the cell
