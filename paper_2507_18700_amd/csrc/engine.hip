@@ -250,6 +250,70 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
         __syncthreads();
 
         // ------------------------------------------------------ site loop
+        // Vertical input of 2D position qn: from the prefix cache (first
+        // steps of a chain), from the column buffer, or none (row 0, or the
+        // row start, whose vertical input is h(qn-1) itself).
+        auto vt_src = [&](int qn, int &icol_n, int &pos_n) -> int {  // 0 none, 1 cache, 2 column buffer
+            if (DIMS != 2 || qn >= N) return 0;
+            const int st = order_site(qn, Lx), jr = qn / Lx;
+            icol_n = st - jr * Lx;
+            if (jr == 0) return 0;
+            pos_n = site_pos(st - Lx, Lx);
+            if (pos_n == qn - 1) return 0;
+            return pos_n <= p ? 1 : 2;
+        };
+        // REGW variants prefetch the next position's vertical rows into
+        // registers while the current position's MFMAs run.
+        constexpr int NCH = MT * (DH / VEC), PF = (NCH + NT - 1) / NT;
+        float4 pfa[REGW ? PF : 1], pfb[REGW ? PF : 1];
+        auto vt_issue = [&](int qn) {
+            int ic = 0, pn = 0;
+            const int src = vt_src(qn, ic, pn);
+            if (!src) return;
+#pragma unroll
+            for (int i = 0; i < (REGW ? PF : 1); i++) {
+                const int e = tid + i * NT;
+                if (e >= NCH) break;
+                const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
+                if (src == 1) {
+                    const int s = sRow[r];
+                    pfa[i] = pfb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (s >= 0) {
+                        const float *sp = &a.hcache[((int64_t)pn * ns_c + s) * DH + c];
+                        pfa[i] = *(const float4 *)sp;
+                        if (VEC == 8) pfb[i] = *(const float4 *)(sp + 4);
+                    }
+                } else {
+                    pfa[i] = __builtin_bit_cast(float4, *(const uint4 *)&colbuf[((int64_t)ic * MT + r) * DH + c]);
+                }
+            }
+        };
+        auto vt_store = [&](int qn) {
+            int ic = 0, pn = 0;
+            const int src = vt_src(qn, ic, pn);
+            if (!src) return;
+#pragma unroll
+            for (int i = 0; i < (REGW ? PF : 1); i++) {
+                const int e = tid + i * NT;
+                if (e >= NCH) break;
+                const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
+                T *d = &sV[r * H_LD + c];
+                if (src == 1) {
+                    d[0] = cvt<P>(pfa[i].x);
+                    d[1] = cvt<P>(pfa[i].y);
+                    d[2] = cvt<P>(pfa[i].z);
+                    d[3] = cvt<P>(pfa[i].w);
+                    if (VEC == 8) {
+                        d[4] = cvt<P>(pfb[i].x);
+                        d[5] = cvt<P>(pfb[i].y);
+                        d[6] = cvt<P>(pfb[i].z);
+                        d[7] = cvt<P>(pfb[i].w);
+                    }
+                } else {
+                    *(uint4 *)d = __builtin_bit_cast(uint4, pfa[i]);
+                }
+            }
+        };
         for (int q = p + 1; q < N; q++) {
             const int cb = q & 1, pb = cb ^ 1;
             const int site = order_site(q, Lx);
@@ -262,8 +326,8 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             const bool vt_prev = has_vt && pos_vt == q - 1;   // vertical input is h(q-1) (row start)
             const bool vt_load = has_vt && pos_vt < q - 1;    // vertical input from cache / column buffer
 
-            // 1. operands: vertical hidden input and the indicator block
-            if (DIMS == 2 && vt_load) {
+            // 1. operands: vertical hidden input (unless prefetched) and the indicator block
+            if (DIMS == 2 && vt_load && (!REGW || q == p + 1)) {
                 const bool from_cache = pos_vt <= p;
                 for (int e = tid; e < MT * (DH / VEC); e += NT) {
                     const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
@@ -303,6 +367,8 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 }
             }
             __syncthreads();
+
+            if (REGW) vt_issue(q + 1);
 
             // 2.+3. cell contraction on MFMA and the gate algebra (App. A); the
             // new h goes to sH[cb].  With register-resident weights one row
@@ -424,6 +490,8 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                                 cvt<P>(hv[rb][ub][ii]);
             }
             __syncthreads();
+
+            if (REGW) vt_store(q + 1);
 
             // the column buffer keeps h for the vertical input of the next row
             if (DIMS == 2 && jrow + 1 < Ly && ((q + 1) % Lx) != 0) {
@@ -547,7 +615,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                     z1 += sLog[x][r][3];
                 }
                 const float mx = fmaxf(l0, l1);
-                const float lse = mx + log1pf(expf(-fabsf(l0 - l1)));
+                const float lse = mx + __logf(1.0f + __expf(-fabsf(l0 - l1)));
                 const float ls0 = l0 - lse, ls1 = l1 - lse;
                 const float ph0 = cplx ? PI_F * softsignf_(z0) : 0.f;
                 const float ph1 = cplx ? PI_F * softsignf_(z1) : 0.f;
@@ -563,7 +631,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                         const uint32_t wsel = (q & 3) == 0 ? c4[0] : (q & 3) == 1 ? c4[1] : (q & 3) == 2 ? c4[2] : c4[3];
                         uni = (float)(wsel >> 8) * (1.0f / 16777216.0f);
                     }
-                    sg = (uni < expf(ls0)) ? 0 : 1;
+                    sg = (uni < __expf(ls0)) ? 0 : 1;
                     sSig[r * N + site] = (uint8_t)sg;
                 } else {
                     sg = sSig[r * N + site];
