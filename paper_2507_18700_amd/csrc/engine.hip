@@ -21,6 +21,8 @@
 // while the new h is written), so no operand copies are made.  With REGW the
 // cell weights stay in registers for the whole persistent launch and the GLU
 // weights in LDS; otherwise both stream from L2.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace vmc {
@@ -435,22 +437,44 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 }
             };
             if (REGW) {
+                // branch-free variants per input pattern; the MFMAs of row
+                // block rb+1 are issued ahead of the epilogue of block rb
+                auto cell_phase = [&](auto HZ, auto VT) {
+                    auto block = [&](int rb, f32x4_t *acc) {
 #pragma unroll
-                for (int rb = 0; rb < RB; rb++) {
-                    f32x4_t acc[3 * UB];
+                        for (int c = 0; c < 3 * UB; c++) acc[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int c = 0; c < 3 * UB; c++) acc[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+                        for (int ks = 0; ks < NKS; ks++) {
+                            const int blk = ks / NKB;
+                            const bool is_x = ks == NKS - 1;
+                            if (!is_x && blk == 0 && !decltype(HZ)::value) continue;
+                            if (!is_x && blk == 1 && !decltype(VT)::value) continue;
+                            const uint4 af = a_frag(rb, ks);
 #pragma unroll
-                    for (int ks = 0; ks < NKS; ks++) {
-                        if (!ks_active(ks)) continue;
-                        const uint4 af = a_frag(rb, ks);
+                            for (int g = 0; g < 3; g++)
 #pragma unroll
-                        for (int g = 0; g < 3; g++)
+                                for (int ub = 0; ub < UB; ub++)
+                                    P::mma(acc[g * UB + ub], af, wreg[REGW ? g : 0][REGW ? ks : 0][REGW ? ub : 0]);
+                        }
+                    };
+                    f32x4_t acc[2][3 * UB];
+                    block(0, acc[0]);
 #pragma unroll
-                            for (int ub = 0; ub < UB; ub++)
-                                P::mma(acc[g * UB + ub], af, wreg[REGW ? g : 0][REGW ? ks : 0][REGW ? ub : 0]);
+                    for (int rb = 0; rb < RB; rb++) {
+                        if (rb + 1 < RB) block(rb + 1, acc[(rb + 1) & 1]);
+                        epilogue(rb, acc[rb & 1]);
                     }
-                    epilogue(rb, acc);
+                };
+                using T1 = std::integral_constant<bool, true>;
+                using T0 = std::integral_constant<bool, false>;
+                if (DIMS == 1) {
+                    if (has_hz) cell_phase(T1{}, T0{});
+                    else cell_phase(T0{}, T0{});
+                } else {
+                    if (has_hz && has_vt) cell_phase(T1{}, T1{});
+                    else if (has_hz) cell_phase(T1{}, T0{});
+                    else if (has_vt) cell_phase(T0{}, T1{});
+                    else cell_phase(T0{}, T0{});
                 }
             } else {
                 f32x4_t acc[RB][3 * UB];
@@ -559,9 +583,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 #pragma unroll
                 for (int rb = 0; rb < RB; rb++) glu_epilogue(rb, nullptr);
             } else if (REGW) {
-#pragma unroll
-                for (int rb = 0; rb < RB; rb++) {
-                    f32x4_t acc2[2 * UB];
+                auto gblock = [&](int rb, f32x4_t *acc2) {
 #pragma unroll
                     for (int c = 0; c < 2 * UB; c++) acc2[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -575,7 +597,13 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                                 P::mma(acc2[g * UB + ub], af, *(const uint4 *)&sG[n * GLD + kk + VEC * lq]);
                             }
                     }
-                    glu_epilogue(rb, acc2);
+                };
+                f32x4_t acc2[2][2 * UB];
+                gblock(0, acc2[0]);
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++) {
+                    if (rb + 1 < RB) gblock(rb + 1, acc2[(rb + 1) & 1]);
+                    glu_epilogue(rb, acc2[rb & 1]);
                 }
             } else {
                 f32x4_t acc2[RB][2 * UB];
