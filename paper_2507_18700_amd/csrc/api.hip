@@ -19,12 +19,9 @@ hipError_t launch_assemble(const vmc_ham &H, int Lx, int Ly, int64_t ns, const u
 int engine_kpx(const Dims &d);
 int forward_tile_rows(int DH);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
-hipError_t launch_grad(const Dims &d, const void *BcT, const void *BgT, const float *E, const float *Hd,
-                       int64_t ns, const uint8_t *cfg, const float *hcache, const float *act,
-                       const double *eloc, const double *weights, double *stats, float *dcell,
-                       float *dglu, float *dhead, void *dcol, float *part, int G, double *grad_st,
-                       double *grad, hipStream_t st);
-void grad_sizes(const Dims &d, int64_t ns, int *G, size_t *part_floats, size_t *gst_doubles);
+hipError_t launch_grad(const GradBufs &b, hipStream_t st);
+void grad_sizes(const Dims &d, int64_t ns, size_t *part_floats);
+int64_t grad_nsp(int64_t ns);
 hipError_t launch_grow(const vmc_model &from, const float *p0, int new_dh, uint64_t seed, double noise,
                        float *p1, const float *m0, const float *v0, float *m1, float *v1,
                        int64_t n_to, hipStream_t st);
@@ -87,9 +84,10 @@ struct WsMap {
     size_t hcache, lpc, phc, pre, dsuf;
     size_t cnt, list_off, tile_start, tile_counter, list;
     size_t colbuf;
-    size_t act, dcell, dglu, dhead, dcol, part, gst, stats;
+    size_t act, hT, gT, xT, dtc, dtg, dth, dcol, part, stats;
     size_t total;
-    int chain_grid, fwd_grid, NC, G;
+    int chain_grid, fwd_grid, NC;
+    int64_t nsp;
 };
 
 static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
@@ -132,14 +130,17 @@ static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
     const size_t AW = (size_t)(NA + 3) * d.DH + 4;
     w.act = put((size_t)d.N * ns * AW * 4);
     const int nd_cell = d.dims == 1 ? 4 * d.DH : 3 * d.DH;
-    w.dcell = put((size_t)d.N * ns * nd_cell * 4);
-    w.dglu = put(d.glu ? (size_t)d.N * ns * 2 * d.DH * 4 : 16);
-    w.dhead = put((size_t)d.N * ns * 4 * 4);
+    w.nsp = grad_nsp(ns);
+    w.hT = put((size_t)d.N * d.DH * w.nsp * es);
+    w.gT = put(d.glu ? (size_t)d.N * d.DH * w.nsp * es : 16);
+    w.dtc = put((size_t)d.N * nd_cell * w.nsp * es);
+    w.dtg = put(d.glu ? (size_t)d.N * 2 * d.DH * w.nsp * es : 16);
+    w.dth = put((size_t)d.N * 4 * w.nsp * es);
     w.dcol = put(d.dims == 2 ? (size_t)w.fwd_grid * d.Lx * MT * d.DH * 4 : 16);
-    size_t part_floats = 0, gst_doubles = 0;
-    grad_sizes(d, ns, &w.G, &part_floats, &gst_doubles);
+    w.xT = put((size_t)d.N * 5 * w.nsp * es);
+    size_t part_floats = 0;
+    grad_sizes(d, ns, &part_floats);
     w.part = put(part_floats * 4);
-    w.gst = put(gst_doubles * 8);
     w.stats = put(8 * 8);
     w.total = o;
     return w;
@@ -301,12 +302,29 @@ static vmc_status eloc_from_cache(const Dims &d, const WsMap &w, void *ws, const
 static vmc_status grad_from_cache(const Dims &d, const WsMap &w, void *ws, int64_t ns, const uint8_t *configs,
                                   const double *eloc, const double *weights, double *grad, double *stats,
                                   hipStream_t st) {
-    double *st_out = stats ? stats : at<double>(ws, w.stats);
-    return hip_status(launch_grad(d, at<void>(ws, w.BcT), at<void>(ws, w.BgT), at<float>(ws, w.E),
-                                  at<float>(ws, w.Hd), ns, configs, at<float>(ws, w.hcache), at<float>(ws, w.act),
-                                  eloc, weights, st_out, at<float>(ws, w.dcell), at<float>(ws, w.dglu),
-                                  at<float>(ws, w.dhead), at<void>(ws, w.dcol), at<float>(ws, w.part), w.G,
-                                  at<double>(ws, w.gst), grad, st));
+    GradBufs b;
+    b.d = d;
+    b.BcT = at<void>(ws, w.BcT);
+    b.BgT = at<void>(ws, w.BgT);
+    b.E = at<float>(ws, w.E);
+    b.Hd = at<float>(ws, w.Hd);
+    b.ns = ns;
+    b.cfg = configs;
+    b.hcache = at<float>(ws, w.hcache);
+    b.act = at<float>(ws, w.act);
+    b.eloc = eloc;
+    b.weights = weights;
+    b.stats = stats ? stats : at<double>(ws, w.stats);
+    b.dtc = at<void>(ws, w.dtc);
+    b.dtg = at<void>(ws, w.dtg);
+    b.dth = at<void>(ws, w.dth);
+    b.hT = at<void>(ws, w.hT);
+    b.gT = at<void>(ws, w.gT);
+    b.dcol = at<void>(ws, w.dcol);
+    b.xT = at<void>(ws, w.xT);
+    b.part = at<float>(ws, w.part);
+    b.grad = grad;
+    return hip_status(launch_grad(b, st));
 }
 
 vmc_status local_energy(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns,
@@ -349,6 +367,9 @@ vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const u
     a.cfg_in = configs;
     a.hcache = at<float>(ws, w.hcache);
     a.act = at<float>(ws, w.act);
+    a.hT = at<void>(ws, w.hT);
+    a.gT = at<void>(ws, w.gT);
+    a.nsp = w.nsp;
     e = launch_forward(a, MODE_LOGPSI, 1, 0, 1, w.fwd_grid, st);
     if (e != hipSuccess) return VMC_EDEVICE;
     return grad_from_cache(d, w, ws, ns, configs, eloc, weights, grad, stats, st);
@@ -380,6 +401,9 @@ vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, i
     a.phc = at<float>(ws, w.phc);
     a.pre = at<double2>(ws, w.pre);
     a.act = at<float>(ws, w.act);
+    a.hT = at<void>(ws, w.hT);
+    a.gT = at<void>(ws, w.gT);
+    a.nsp = w.nsp;
     if (phase && !d.cplx) {
         e = launch_fill(phase, ns, 0.0f, st);
         if (e != hipSuccess) return VMC_EDEVICE;

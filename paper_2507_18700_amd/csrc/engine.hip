@@ -421,7 +421,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                             h = uu * c + (1.0f - uu) * g2;
                             s0 = c; s1 = uu; s2 = g2;
                         }
-                        hv[rb][ub][ii] = h;
+                        hv[rb][ub][ii] = (STORE && s < 0) ? 0.f : h;
                         if (DIMS == 2) sH[cb][r * H_LD + u] = cvt<P>(h);
                         if (s >= 0) {
                             if (store_h) a.hcache[((int64_t)q * ns_c + s) * DH + u] = h;
@@ -432,6 +432,17 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                                 ar[2 * DH + u] = s2;
                                 if (DIMS == 1) ar[3 * DH + u] = s3;
                             }
+                        }
+                    }
+                }
+                if (store_act) {
+                    const int64_t s0 = e0 + wr * C::RW + rb * 16 + 4 * lq;
+                    if (s0 < a.nsp) {
+#pragma unroll
+                        for (int ub = 0; ub < UB; ub++) {
+                            const int u = wu * C::UW + ub * 16 + l16;
+                            store4<P>((T *)a.hT + ((int64_t)q * DH + u) * a.nsp + s0, hv[rb][ub][0], hv[rb][ub][1],
+                                      hv[rb][ub][2], hv[rb][ub][3]);
                         }
                     }
                 }
@@ -527,7 +538,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 
             // 4. GLU (MFMA) and heads (FP32)
             auto glu_epilogue = [&](int rb, const f32x4_t *acc2) {
-                float part[4][4];
+                float part[4][4], gk[UB][4];
 #pragma unroll
                 for (int ii = 0; ii < 4; ii++)
 #pragma unroll
@@ -559,6 +570,18 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                         if (cplx) {
                             part[ii][2] += hw[2][ub] * g;
                             part[ii][3] += hw[3][ub] * g;
+                        }
+                        if (STORE) gk[ub][ii] = s >= 0 ? g : 0.f;
+                    }
+                }
+                if (store_act && glu) {
+                    const int64_t s0 = e0 + wr * C::RW + rb * 16 + 4 * lq;
+                    if (s0 < a.nsp) {
+#pragma unroll
+                        for (int ub = 0; ub < UB; ub++) {
+                            const int u = wu * C::UW + ub * 16 + l16;
+                            store4<P>((T *)a.gT + ((int64_t)q * DH + u) * a.nsp + s0, gk[ub][0], gk[ub][1], gk[ub][2],
+                                      gk[ub][3]);
                         }
                     }
                 }

@@ -2,8 +2,10 @@
 // a reverse sweep (backpropagation through the autoregressive chain) that
 // produces the per-(position, sample) deltas of every contraction, and the
 // weight gradients as contractions of those deltas with the layer inputs over
-// all (position, sample) rows: FP32 tile partials on MFMA, summed across tiles
-// in FP64 in a fixed order.
+// all (position, sample) pairs.  Deltas and inputs are stored transposed,
+// [position][feature][sample], so the contraction over samples reads MFMA
+// fragments straight from memory; one partial per position (FP32 MFMA
+// accumulation), summed over positions in FP64 in a fixed order.
 //
 // With E held constant, the gradient is that of the surrogate
 //   L = sum_s [a_s log P(sigma_s) + b_s phi(sigma_s)],
@@ -15,7 +17,6 @@
 namespace vmc {
 
 constexpr int DW_TILE = 128;    // output tile of the weight-gradient contraction
-constexpr int DW_ROWS = 4096;   // rows per FP32 partial (summed in FP64 afterwards)
 
 // ------------------------------------------------------------- statistics
 
@@ -77,9 +78,11 @@ struct BwdArgs {
     const uint8_t *cfg;
     const float *hcache, *act;
     const double *eloc, *w, *stats;
-    float *dcell, *dglu, *dhead;
-    float *dcol;  // [grid][Lx][MT][DH]
+    void *dtc, *dtg, *dth;  // transposed deltas: cell [N][NDC][nsp], GLU [N][2DH][nsp], heads [N][4][nsp]
+    int64_t nsp;            // sample stride of the transposed arrays (ns rounded up to 32)
+    float *dcol;            // [grid][Lx][MT][DH]
 };
+
 
 // Reverse sweep over the order positions for a tile of samples.  At each
 // position: head deltas (softmax / softsign derivatives, Eqs. 3, 5), GLU
@@ -179,11 +182,14 @@ __global__ __launch_bounds__(256) void rnn_backward(BwdArgs a) {
                     if (sg) z1 = dz;
                     else z0 = dz;
                 }
-                float *dh = a.dhead + ((int64_t)q * ns + s) * 4;
-                dh[0] = d0;
-                dh[1] = d1;
-                dh[2] = z0;
-                dh[3] = z1;
+            }
+            const int64_t sg_ = e0 + tid;
+            if (sg_ < a.nsp) {
+                T *dh = (T *)a.dth + (int64_t)q * 4 * a.nsp + sg_;
+                dh[0] = P::from_float(d0);
+                dh[a.nsp] = P::from_float(d1);
+                dh[2 * a.nsp] = P::from_float(z0);
+                dh[3 * a.nsp] = P::from_float(z1);
             }
             sDL[tid][0] = d0;
             sDL[tid][1] = d1;
@@ -193,7 +199,7 @@ __global__ __launch_bounds__(256) void rnn_backward(BwdArgs a) {
         __syncthreads();
 
         // (b) head -> g, GLU deltas
-        float dgv[RB][UB][4];
+        float dgv[RB][UB][4], gd1[RB][UB][4], gd2[RB][UB][4];
 #pragma unroll
         for (int rb = 0; rb < RB; rb++)
 #pragma unroll
@@ -214,15 +220,29 @@ __global__ __launch_bounds__(256) void rnn_backward(BwdArgs a) {
                             const float sg2 = sigmoidf_(a2);
                             d1 = dg * sg2;
                             d2 = dg * a1 * sg2 * (1.0f - sg2);
-                            float *gd = a.dglu + ((int64_t)q * ns + s) * 2 * DH;
-                            gd[u] = d1;
-                            gd[DH + u] = d2;
                         }
+                        gd1[rb][ub][ii] = d1;
+                        gd2[rb][ub][ii] = d2;
                         sD2[r * D2_LD + u] = P::from_float(d1);
                         sD2[r * D2_LD + DH + u] = P::from_float(d2);
                     }
                 }
             }
+        if (glu) {
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++) {
+                const int64_t s0 = e0 + wr * C::RW + rb * 16 + 4 * (lane >> 4);
+                if (s0 >= a.nsp) continue;
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    const int u = wu * C::UW + ub * 16 + (lane & 15);
+                    T *dst = (T *)a.dtg + ((int64_t)q * 2 * DH + u) * a.nsp + s0;
+                    store4<P>(dst, gd1[rb][ub][0], gd1[rb][ub][1], gd1[rb][ub][2], gd1[rb][ub][3]);
+                    store4<P>(dst + (int64_t)DH * a.nsp, gd2[rb][ub][0], gd2[rb][ub][1], gd2[rb][ub][2],
+                              gd2[rb][ub][3]);
+                }
+            }
+        }
         __syncthreads();
 
         // (c) GLU input gradient: dh_glu = [d1 | d2] . [W_1 ; W_2]  (MFMA)
@@ -254,6 +274,7 @@ __global__ __launch_bounds__(256) void rnn_backward(BwdArgs a) {
 
         // (d) total dh and the cell deltas (App. A gate algebra, reversed)
         float direct[RB][UB][4];  // 1D: dh (1-u), the gradient reaching h_{n-1} directly
+        float cg[4][RB][UB][4];   // cell deltas per gate, kept for the transposed store
 #pragma unroll
         for (int rb = 0; rb < RB; rb++)
 #pragma unroll
@@ -286,17 +307,30 @@ __global__ __launch_bounds__(256) void rnn_backward(BwdArgs a) {
                             g1 = du * uu * (1.0f - uu);     // update-gate pre-activation
                             g2 = dh * (1.0f - uu);          // U h'
                         }
-                        float *cd = a.dcell + ((int64_t)q * ns + s) * NDC;
-                        cd[u] = g0;
-                        cd[DH + u] = g1;
-                        cd[2 * DH + u] = g2;
-                        if (DIMS == 1) cd[3 * DH + u] = g3;
                     }
+                    cg[0][rb][ub][ii] = g0;
+                    cg[1][rb][ub][ii] = g1;
+                    cg[2][rb][ub][ii] = g2;
+                    cg[3][rb][ub][ii] = g3;
                     sD3[r * D3_LD + u] = P::from_float(g0);
                     sD3[r * D3_LD + DH + u] = P::from_float(g1);
                     sD3[r * D3_LD + 2 * DH + u] = P::from_float(g2);
                 }
             }
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++) {
+            const int64_t s0 = e0 + wr * C::RW + rb * 16 + 4 * (lane >> 4);
+            if (s0 >= a.nsp) continue;
+#pragma unroll
+            for (int ub = 0; ub < UB; ub++) {
+                const int u = wu * C::UW + ub * 16 + (lane & 15);
+#pragma unroll
+                for (int g = 0; g < (DIMS == 1 ? 4 : 3); g++) {
+                    T *dst = (T *)a.dtc + ((int64_t)q * NDC + g * DH + u) * a.nsp + s0;
+                    store4<P>(dst, cg[g][rb][ub][0], cg[g][rb][ub][1], cg[g][rb][ub][2], cg[g][rb][ub][3]);
+                }
+            }
+        }
         __syncthreads();
 
         // (e) cell input gradient: dA = delta . B_c  (MFMA); route to predecessors
@@ -351,165 +385,125 @@ __global__ __launch_bounds__(256) void rnn_backward(BwdArgs a) {
 
 struct DwArgs {
     Dims d;
-    int seg;             // 0 cell, 1 GLU, 2 heads
-    int64_t ns, R;       // R = N * ns rows, row = q * ns + s
-    const float *D;      // [R][MD] deltas
-    int MD, KX, Mp, Kp;  // delta row width, input row width, padded output dims
-    const float *hcache, *act;
-    const uint8_t *cfg;
-    float *part;         // [G][Mp][Kp]
+    int seg;              // 0 cell, 1 GLU, 2 heads
+    int64_t ns, nsp;      // samples, padded sample stride
+    const void *A;        // transposed deltas [N][MD][nsp]
+    int MD, K, Mp, Kp;    // delta rows, hidden input columns, padded output dims
+    const void *hT, *gT;  // transposed hidden states / GLU outputs [N][DH][nsp]
+    const void *xT;       // transposed extra inputs [N][5][nsp]: 1, onehot_hz(2), onehot_vt(2)
+    float *part;          // [N][Mp][Kp]
 };
 
-// Input row of the contraction for segment `seg` at row (q, s):
-//  cell 1D: [h_{q-1} | 1 | onehot(sigma_{q-1})]
-//  cell 2D: [h_hz | h_vt | 1 | onehot_hz | onehot_vt]
-//  GLU:     [h_q | 1];   heads: [g_q | 1]
-// Described per row by up to two contiguous hidden sources (element offsets
-// into hcache or act, -1 = absent) and up to five extra values.
-struct DwRow {
-    int64_t src0, src1;
-    float ex[5];
-};
-
-__device__ inline DwRow dw_row(const DwArgs &a, int q, int s) {
-    const int DH = a.d.DH, Lx = a.d.Lx, N = a.d.N;
-    const int64_t ns = a.ns;
-    DwRow r;
-    r.src0 = r.src1 = -1;
-    for (int i = 0; i < 5; i++) r.ex[i] = 0.f;
-    r.ex[0] = 1.f;
-    if (a.seg == 1) {
-        r.src0 = ((int64_t)q * ns + s) * DH;
-        return r;
+// Source row of input column k of segment seg at position q: a hidden state
+// (h or g) of some position, one of the extra rows (bias 1, one-hots), or
+// none.  Returns the row pointer offset in elements or -1.
+__device__ inline int64_t dw_source(const DwArgs &a, int q, int k, bool &extra) {
+    const int DH = a.d.DH, Lx = a.d.Lx;
+    const int64_t nsp = a.nsp;
+    extra = false;
+    if (k >= a.K) {
+        const int c = k - a.K;
+        if (c >= (a.seg == 0 ? (a.d.dims == 1 ? 3 : 5) : 1)) return -1;
+        extra = true;
+        return ((int64_t)q * 5 + c) * nsp;
     }
-    if (a.seg == 2) {
-        r.src0 = ((int64_t)q * ns + s) * act_width(a.d.dims, DH) + (nact_per_unit(a.d.dims) + 2) * DH;
-        return r;
-    }
-    const bool has_hz = (q % Lx) != 0;
-    if (a.d.dims == 1) {
-        if (has_hz) {
-            r.src0 = ((int64_t)(q - 1) * ns + s) * DH;
-            const int x = a.cfg[(int64_t)s * N + (q - 1)];
-            r.ex[1 + x] = 1.f;
-        }
-        return r;
-    }
-    const int site = order_site(q, Lx);
-    if (has_hz) {
-        r.src0 = ((int64_t)(q - 1) * ns + s) * DH;
-        r.ex[1 + a.cfg[(int64_t)s * N + order_site(q - 1, Lx)]] = 1.f;
-    }
-    if (q >= Lx) {
-        r.src1 = ((int64_t)site_pos(site - Lx, Lx) * ns + s) * DH;
-        r.ex[3 + a.cfg[(int64_t)s * N + site - Lx]] = 1.f;
-    }
-    return r;
+    if (a.seg != 0) return ((int64_t)q * DH + k) * nsp;
+    if (k < DH) return (q % Lx) != 0 ? ((int64_t)(q - 1) * DH + k) * nsp : -1;
+    if (q < Lx) return -1;
+    return ((int64_t)site_pos(order_site(q, Lx) - Lx, Lx) * DH + (k - DH)) * nsp;
 }
 
-// dW[m][k] partial over DW_ROWS rows: FP32 MFMA 16x16x4 on a 128x128 output
-// tile, 4 waves as 2x2 of 64x64.  Grid (m tiles, k tiles, row chunks).  The
-// deltas and the inputs of 16 rows at a time are staged in LDS with 16-byte
-// loads; each hidden input row is one contiguous source.
-__global__ __launch_bounds__(256) void dw_kernel(DwArgs a) {
-    constexpr int RS = 16, T = DW_TILE, LD = T + 4;
-    __shared__ __align__(16) float sD[RS][LD];
-    __shared__ __align__(16) float sX[RS][LD];
-    __shared__ DwRow sR[RS];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int m0 = blockIdx.x * T, k0 = blockIdx.y * T;
-    const int64_t r0 = (int64_t)blockIdx.z * DW_ROWS;
-    const int64_t r1 = min(r0 + DW_ROWS, a.R);
-    const int wm = (w >> 1) * 64, wk = (w & 1) * 64;
-    const int DH = a.d.DH;
-    const int nhid = (a.seg == 0 && a.d.dims == 2) ? 2 * DH : DH;  // hidden columns of the input
-    const float *xsrc = a.seg == 2 ? a.act : a.hcache;
+// Extra input rows per position: 1, the one-hot of the horizontal
+// predecessor's spin, the one-hot of the vertical predecessor's spin (zeros
+// where the predecessor is absent), transposed [N][5][nsp].
+template <class P>
+__global__ void build_extras(Dims d, int64_t ns, int64_t nsp, const uint8_t *cfg, typename P::store_t *xT) {
+    const int N = d.N, Lx = d.Lx;
+    const int64_t total = (int64_t)N * nsp;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(e / nsp);
+        const int64_t s = e % nsp;
+        float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        if (s < ns) {
+            v[0] = 1.f;
+            if ((q % Lx) != 0) v[1 + cfg[s * N + order_site(q - 1, Lx)]] = 1.f;
+            if (d.dims == 2 && q >= Lx) v[3 + cfg[s * N + order_site(q, Lx) - Lx]] = 1.f;
+        }
+#pragma unroll
+        for (int c = 0; c < 5; c++) xT[((int64_t)q * 5 + c) * nsp + s] = P::from_float(v[c]);
+    }
+}
+
+// dW[m][k] at one position q (grid z): sum over samples of A[q][m][s] X[q][k][s]
+// on MFMA, operands read as 16-byte fragments straight from memory.  128x128
+// output tile, 4 waves as 2x2 of 64x64.
+template <class P>
+__global__ __launch_bounds__(256) void dw_mfma(DwArgs a) {
+    typedef typename P::store_t T;
+    constexpr int VEC = P::VEC, KS = P::KSTEP;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, lq = lane >> 4;
+    const int m0 = blockIdx.x * DW_TILE + (w >> 1) * 64, k0 = blockIdx.y * DW_TILE + (w & 1) * 64;
+    const int q = blockIdx.z;
+    const int64_t nsp = a.nsp;
+    const T *A = (const T *)a.A + (int64_t)q * a.MD * nsp;
+    const T *X = (const T *)(a.seg == 2 && a.d.glu ? a.gT : a.hT);
+    const T *XE = (const T *)a.xT;
+    const T *ap[4];
+    const T *bp[4];
+    bool mon[4], kon[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int m = m0 + 16 * i + l16;
+        mon[i] = (m0 + 16 * i) < a.MD;
+        ap[i] = A + (int64_t)(m < a.MD ? m : 0) * nsp + VEC * lq;
+        bool extra;
+        const int k = k0 + 16 * i + l16;
+        const int64_t off = dw_source(a, q, k, extra);
+        // a 16-column block is live if any of its columns has a source
+        bool live = false;
+        for (int c = 0; c < 16; c++) {
+            bool ex2;
+            live |= dw_source(a, q, k0 + 16 * i + c, ex2) >= 0;
+        }
+        kon[i] = live;
+        bp[i] = off >= 0 ? (extra ? XE : X) + off + VEC * lq : nullptr;
+    }
     f32x4_t acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    // blocks of this wave that hold real output
-    const int mlim = a.MD - (m0 + wm), klim = a.KX - (k0 + wk);
-    for (int64_t rb = r0; rb < r1; rb += RS) {
-        if (tid < RS) {
-            const int64_t row = rb + tid;
-            DwRow r;
-            if (row < r1) {
-                r = dw_row(a, (int)(row / a.ns), (int)(row % a.ns));
-            } else {
-                r.src0 = r.src1 = -1;
-                for (int i = 0; i < 5; i++) r.ex[i] = 0.f;
-            }
-            sR[tid] = r;
+    for (int64_t s0 = 0; s0 < nsp; s0 += KS) {
+        uint4 af[4], bf[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            af[i] = mon[i] ? *(const uint4 *)(ap[i] + s0) : make_uint4(0, 0, 0, 0);
+            bf[i] = bp[i] ? *(const uint4 *)(bp[i] + s0) : make_uint4(0, 0, 0, 0);
         }
-        __syncthreads();
-        for (int e = tid; e < RS * (T / 4); e += 256) {
-            const int rr = e / (T / 4), c = (e % (T / 4)) * 4;
-            const int64_t row = rb + rr;
-            float4 dv = make_float4(0.f, 0.f, 0.f, 0.f), xv = dv;
-            if (row < r1) {
-                const int m = m0 + c;
-                if (m + 3 < a.MD) dv = *(const float4 *)&a.D[row * a.MD + m];
-                else if (m < a.MD) {
-                    dv.x = a.D[row * a.MD + m];
-                    if (m + 1 < a.MD) dv.y = a.D[row * a.MD + m + 1];
-                    if (m + 2 < a.MD) dv.z = a.D[row * a.MD + m + 2];
-                }
-                const int k = k0 + c;
-                const DwRow &R = sR[rr];
-                if (k < nhid) {
-                    const int blk = k >= DH, kk = k - blk * DH;
-                    const int64_t src = blk ? R.src1 : R.src0;
-                    if (src >= 0) xv = *(const float4 *)&xsrc[src + kk];
-                } else {
-                    float t[4];
 #pragma unroll
-                    for (int x = 0; x < 4; x++) {
-                        const int ke = k + x - nhid;
-                        t[x] = (ke < 5) ? R.ex[ke] : 0.f;
-                    }
-                    xv = make_float4(t[0], t[1], t[2], t[3]);
-                }
-            }
-            *(float4 *)&sD[rr][c] = dv;
-            *(float4 *)&sX[rr][c] = xv;
+        for (int i = 0; i < 4; i++) {
+            if (!mon[i]) continue;
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (kon[j]) P::mma(acc[i][j], af[i], bf[j]);
         }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < RS; kk += 4) {
-            float av[4], bv[4];
-#pragma unroll
-            for (int i = 0; i < 4; i++) av[i] = sD[kk + (lane >> 4)][wm + i * 16 + (lane & 15)];
-#pragma unroll
-            for (int j = 0; j < 4; j++) bv[j] = sX[kk + (lane >> 4)][wk + j * 16 + (lane & 15)];
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                if (i * 16 >= mlim) continue;
-#pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    if (j * 16 >= klim) continue;
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-                }
-            }
-        }
-        __syncthreads();
     }
-    float *out = a.part + (int64_t)blockIdx.z * a.Mp * a.Kp;
+    float *out = a.part + (int64_t)q * a.Mp * a.Kp;
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int j = 0; j < 4; j++)
 #pragma unroll
             for (int ii = 0; ii < 4; ii++) {
-                const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + ii;
-                const int k = k0 + wk + j * 16 + (lane & 15);
+                const int m = m0 + i * 16 + 4 * lq + ii;
+                const int k = k0 + j * 16 + l16;
                 out[(int64_t)m * a.Kp + k] = acc[i][j][ii];
             }
 }
 
 // Flat parameter index of the weight-gradient entry (seg, m, k), or -1 for
-// padding and unused combinations.
+// padding and unused combinations.  k < K: hidden input columns; k = K: bias;
+// k = K+1.. : one-hot columns.
 __device__ inline int64_t dw_param(const Dims &d, int seg, int m, int k) {
     const int dh = d.dh, DH = d.DH;
     const ParamLayout L = param_layout(d.dims, dh, d.glu, d.cplx);
@@ -564,16 +558,17 @@ __device__ inline int64_t dw_param(const Dims &d, int seg, int m, int k) {
     return -1;
 }
 
-// FP64 sum of the partials over the row chunks (fixed order), scattered into
-// the flat gradient.
-__global__ void dw_reduce(Dims d, int seg, const float *part, int G, int Mp, int Kp, double *grad) {
-    const int64_t n = (int64_t)Mp * Kp;
+// FP64 sum of the per-position partials (fixed order), scattered into the
+// flat gradient.
+__global__ void dw_reduce(Dims d, int seg, const float *part, int Q, int Mp, int Kp, int K, int MD, double *grad) {
+    const int W = K + 5;
+    const int64_t n = (int64_t)MD * W;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int m = (int)(e / Kp), k = (int)(e % Kp);
+        const int m = (int)(e / W), k = (int)(e % W);
         const int64_t idx = dw_param(d, seg, m, k);
         if (idx < 0) continue;
         double s = 0.0;
-        for (int g = 0; g < G; g++) s += (double)part[(int64_t)g * n + e];
+        for (int q = 0; q < Q; q++) s += (double)part[((int64_t)q * Mp + m) * Kp + k];
         grad[idx] = s;
     }
 }
@@ -586,37 +581,35 @@ __global__ void fill_f64(double *p, int64_t n, double v) {
 // ------------------------------------------------------------------ host
 
 struct SegDims {
-    int MD, KX, Mp, Kp;
+    int MD, K, Mp, Kp;
 };
 
 static SegDims seg_dims(const Dims &d, int seg) {
     SegDims s;
     if (seg == 0) {
         s.MD = d.dims == 1 ? 4 * d.DH : 3 * d.DH;
-        s.KX = d.dims == 1 ? d.DH + 3 : 2 * d.DH + 5;
+        s.K = d.dims == 1 ? d.DH : 2 * d.DH;
     } else if (seg == 1) {
         s.MD = 2 * d.DH;
-        s.KX = d.DH + 1;
+        s.K = d.DH;
     } else {
         s.MD = 4;
-        s.KX = d.DH + 1;
+        s.K = d.DH;
     }
-    s.Kp = cround(s.KX, DW_TILE);
+    s.Kp = cround(s.K + 5, DW_TILE);
     s.Mp = cround(s.MD, DW_TILE);
     return s;
 }
 
-void grad_sizes(const Dims &d, int64_t ns, int *G, size_t *part_floats, size_t *gst_doubles) {
-    const int64_t R = (int64_t)d.N * ns;
-    *G = (int)((R + DW_ROWS - 1) / DW_ROWS);
+int64_t grad_nsp(int64_t ns) { return (ns + 31) / 32 * 32; }
+
+void grad_sizes(const Dims &d, int64_t ns, size_t *part_floats) {
     size_t mx = 0;
     for (int seg = 0; seg < 3; seg++) {
         SegDims s = seg_dims(d, seg);
-        size_t n = (size_t)s.Mp * s.Kp;
-        if (n > mx) mx = n;
+        mx = (size_t)s.Mp * s.Kp > mx ? (size_t)s.Mp * s.Kp : mx;
     }
-    *part_floats = (size_t)(*G) * mx;
-    *gst_doubles = 16;
+    *part_floats = (size_t)d.N * mx;
 }
 
 template <class P, int DIMS, int DH>
@@ -642,64 +635,77 @@ static hipError_t launch_bwd_d(const BwdArgs &a, int grid, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
+template <class P>
+static void launch_dw_p(const DwArgs &a, const SegDims &sd, hipStream_t st) {
+    dim3 grd(sd.Mp / DW_TILE, sd.Kp / DW_TILE, a.d.N);
+    hipLaunchKernelGGL(dw_mfma<P>, grd, dim3(256), 0, st, a);
+}
+
 int forward_tile_rows(int DH);
 
-hipError_t launch_grad(const Dims &d, const void *BcT, const void *BgT, const float *E, const float *Hd,
-                       int64_t ns, const uint8_t *cfg, const float *hcache, const float *act,
-                       const double *eloc, const double *weights, double *stats, float *dcell,
-                       float *dglu, float *dhead, void *dcol, float *part, int G, double *grad_st,
-                       double *grad, hipStream_t st) {
-    hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(1024), 0, st, ns, eloc, weights, stats);
-    BwdArgs b;
-    b.d = d;
-    b.BcT = BcT;
-    b.BgT = BgT;
-    b.E = E;
-    b.Hd = Hd;
-    b.ns = ns;
-    b.cfg = cfg;
-    b.hcache = hcache;
-    b.act = act;
-    b.eloc = eloc;
-    b.w = weights;
-    b.stats = stats;
-    b.dcell = dcell;
-    b.dglu = dglu;
-    b.dhead = dhead;
-    b.dcol = (float *)dcol;
+hipError_t launch_grad(const GradBufs &b, hipStream_t st) {
+    const Dims &d = b.d;
+    hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(1024), 0, st, b.ns, b.eloc, b.weights, b.stats);
+    BwdArgs bw;
+    bw.d = d;
+    bw.BcT = b.BcT;
+    bw.BgT = b.BgT;
+    bw.E = b.E;
+    bw.Hd = b.Hd;
+    bw.ns = b.ns;
+    bw.cfg = b.cfg;
+    bw.hcache = b.hcache;
+    bw.act = b.act;
+    bw.eloc = b.eloc;
+    bw.w = b.weights;
+    bw.stats = b.stats;
+    bw.dtc = b.dtc;
+    bw.dtg = b.dtg;
+    bw.dth = b.dth;
+    bw.nsp = grad_nsp(b.ns);
+    bw.dcol = (float *)b.dcol;
     const int MT = forward_tile_rows(d.DH);
-    const int grid = (int)((ns + MT - 1) / MT);
+    const int grid = (int)((b.ns + MT - 1) / MT);
     hipError_t e;
     if (d.prec == VMC_BF16)
-        e = d.dims == 1 ? launch_bwd_d<BF16, 1>(b, grid, st) : launch_bwd_d<BF16, 2>(b, grid, st);
+        e = d.dims == 1 ? launch_bwd_d<BF16, 1>(bw, grid, st) : launch_bwd_d<BF16, 2>(bw, grid, st);
     else
-        e = d.dims == 1 ? launch_bwd_d<F32, 1>(b, grid, st) : launch_bwd_d<F32, 2>(b, grid, st);
+        e = d.dims == 1 ? launch_bwd_d<F32, 1>(bw, grid, st) : launch_bwd_d<F32, 2>(bw, grid, st);
     if (e != hipSuccess) return e;
+    {
+        const int64_t nsp = grad_nsp(b.ns), tot = (int64_t)d.N * nsp;
+        const int g2 = (int)((tot + 255) / 256 < 8192 ? (tot + 255) / 256 : 8192);
+        if (d.prec == VMC_BF16)
+            hipLaunchKernelGGL(build_extras<BF16>, dim3(g2), dim3(256), 0, st, d, b.ns, nsp, b.cfg, (uint16_t *)b.xT);
+        else
+            hipLaunchKernelGGL(build_extras<F32>, dim3(g2), dim3(256), 0, st, d, b.ns, nsp, b.cfg, (float *)b.xT);
+    }
     const int64_t P = param_layout(d.dims, d.dh, d.glu, d.cplx).total;
     hipLaunchKernelGGL(fill_f64, dim3((int)((P + 255) / 256 < 4096 ? (P + 255) / 256 : 4096)), dim3(256), 0, st,
-                       grad, P, 0.0);
+                       b.grad, P, 0.0);
     for (int seg = 0; seg < 3; seg++) {
         if (seg == 1 && !d.glu) continue;
         SegDims sd = seg_dims(d, seg);
         DwArgs a;
         a.d = d;
         a.seg = seg;
-        a.ns = ns;
-        a.R = (int64_t)d.N * ns;
-        a.D = seg == 0 ? dcell : seg == 1 ? dglu : dhead;
+        a.ns = b.ns;
+        a.nsp = grad_nsp(b.ns);
+        a.A = seg == 0 ? b.dtc : seg == 1 ? b.dtg : b.dth;
         a.MD = sd.MD;
-        a.KX = sd.KX;
+        a.K = sd.K;
         a.Mp = sd.Mp;
         a.Kp = sd.Kp;
-        a.hcache = hcache;
-        a.act = act;
-        a.cfg = cfg;
-        a.part = part;
-        dim3 grd(sd.Mp / DW_TILE, sd.Kp / DW_TILE, G);
-        hipLaunchKernelGGL(dw_kernel, grd, dim3(256), 0, st, a);
-        const int64_t n = (int64_t)sd.Mp * sd.Kp;
+        a.hT = b.hT;
+        a.gT = b.gT;
+        a.xT = b.xT;
+        a.part = b.part;
+        if (d.prec == VMC_BF16) launch_dw_p<BF16>(a, sd, st);
+        else launch_dw_p<F32>(a, sd, st);
+        const int64_t n = (int64_t)sd.MD * (sd.K + 5);
         int rg = (int)((n + 255) / 256);
-        hipLaunchKernelGGL(dw_reduce, dim3(rg), dim3(256), 0, st, d, seg, part, G, sd.Mp, sd.Kp, grad);
+        hipLaunchKernelGGL(dw_reduce, dim3(rg), dim3(256), 0, st, d, seg, b.part, d.N, sd.Mp, sd.Kp, sd.K, sd.MD,
+                           b.grad);
     }
     return hipGetLastError();
 }

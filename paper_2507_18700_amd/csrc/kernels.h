@@ -23,7 +23,8 @@ struct FwdArgs {
     float *lpc, *phc;        // [ns][N][2] log-conditionals, phase conditionals
     double2 *pre;            // [ns][N] running (log P, phase) after each position, FP64
     float *act;              // [N][ns][NACT*DH] activations for the backward
-    float *ain;              // [N][ns][KA] augmented cell inputs for the backward
+    void *hT, *gT;           // with act: transposed h and GLU output [N][DH][nsp] (store_t)
+    int64_t nsp;             // sample stride of the transposed arrays
     int64_t ns_cache;        // row count of the cache arrays
     // per-workgroup scratch: column buffer of the 2D chain [grid][Lx][MT][DH]
     void *colbuf;
@@ -37,6 +38,39 @@ struct FwdArgs {
 };
 
 enum { MODE_SAMPLE = 0, MODE_LOGPSI = 1, MODE_CHAIN = 2 };
+
+// Buffers of the gradient (vmc_grad after its forward pass).
+struct GradBufs {
+    Dims d;
+    const void *BcT, *BgT;
+    const float *E, *Hd;
+    int64_t ns;
+    const uint8_t *cfg;
+    const float *hcache, *act;
+    const double *eloc, *weights;
+    double *stats;
+    void *dtc, *dtg, *dth;  // transposed deltas (cell, GLU, heads)
+    const void *hT, *gT;    // transposed hidden states and GLU outputs
+    void *xT;               // transposed extra inputs (bias, one-hots)
+    void *dcol;
+    float *part;
+    double *grad;
+};
+
+// Four consecutive samples of one transposed feature row, as one store.
+template <class P>
+__device__ inline void store4(typename P::store_t *dst, float a0, float a1, float a2, float a3);
+template <>
+__device__ inline void store4<F32>(float *dst, float a0, float a1, float a2, float a3) {
+    *(float4 *)dst = make_float4(a0, a1, a2, a3);
+}
+template <>
+__device__ inline void store4<BF16>(uint16_t *dst, float a0, float a1, float a2, float a3) {
+    uint2 v;
+    v.x = (uint32_t)f2bf(a0) | ((uint32_t)f2bf(a1) << 16);
+    v.y = (uint32_t)f2bf(a2) | ((uint32_t)f2bf(a3) << 16);
+    *(uint2 *)dst = v;
+}
 
 __host__ __device__ constexpr int cround(int x, int m) { return (x + m - 1) / m * m; }
 
