@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvmcrnn.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "engine.hip", "forward.hip", "grad.hip", "grow.hip"]
+SOURCES = ["api.hip", "engine.hip", "backward.hip", "forward.hip", "grad.hip", "grow.hip"]
 ARCH = "gfx950"
 
 

@@ -18,6 +18,7 @@ hipError_t launch_assemble(const vmc_ham &H, int Lx, int Ly, int64_t ns, const u
                            double *eloc, hipStream_t st);
 int engine_kpx(const Dims &d);
 int forward_tile_rows(int DH);
+int backward_tile_rows(int DH);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
 hipError_t launch_grad(const GradBufs &b, hipStream_t st);
 void grad_sizes(const Dims &d, int64_t ns, size_t *part_floats);
@@ -84,7 +85,7 @@ struct WsMap {
     size_t hcache, lpc, phc, pre, dsuf;
     size_t cnt, list_off, tile_start, tile_counter, list;
     size_t colbuf;
-    size_t act, hT, gT, xT, dtc, dtg, dth, dcol, part, stats;
+    size_t act, lgT, hT, gT, xT, dtc, dtg, dth, dcol, part, stats;
     size_t total;
     int chain_grid, fwd_grid, NC;
     int64_t nsp;
@@ -126,17 +127,17 @@ static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
     const int g = w.fwd_grid > w.chain_grid ? w.fwd_grid : w.chain_grid;
     w.colbuf = put(d.dims == 2 ? (size_t)g * d.Lx * MT * d.DH * es : 16);
     // backward
-    const int NA = nact_per_unit(d.dims);
-    const size_t AW = (size_t)(NA + 3) * d.DH + 4;
-    w.act = put((size_t)d.N * ns * AW * 4);
     const int nd_cell = d.dims == 1 ? 4 * d.DH : 3 * d.DH;
     w.nsp = grad_nsp(ns);
+    w.act = put((size_t)d.N * act_feats(d.dims) * d.DH * w.nsp * 4);
+    w.lgT = put((size_t)d.N * 4 * w.nsp * 4);
     w.hT = put((size_t)d.N * d.DH * w.nsp * es);
     w.gT = put(d.glu ? (size_t)d.N * d.DH * w.nsp * es : 16);
     w.dtc = put((size_t)d.N * nd_cell * w.nsp * es);
     w.dtg = put(d.glu ? (size_t)d.N * 2 * d.DH * w.nsp * es : 16);
     w.dth = put((size_t)d.N * 4 * w.nsp * es);
-    w.dcol = put(d.dims == 2 ? (size_t)w.fwd_grid * d.Lx * MT * d.DH * 4 : 16);
+    const int MTB = backward_tile_rows(d.DH);
+    w.dcol = put(d.dims == 2 ? (size_t)((w.nsp + MTB - 1) / MTB) * d.Lx * MTB * d.DH * 4 : 16);
     w.xT = put((size_t)d.N * 5 * w.nsp * es);
     size_t part_floats = 0;
     grad_sizes(d, ns, &part_floats);
@@ -312,6 +313,7 @@ static vmc_status grad_from_cache(const Dims &d, const WsMap &w, void *ws, int64
     b.cfg = configs;
     b.hcache = at<float>(ws, w.hcache);
     b.act = at<float>(ws, w.act);
+    b.lgT = at<float>(ws, w.lgT);
     b.eloc = eloc;
     b.weights = weights;
     b.stats = stats ? stats : at<double>(ws, w.stats);
@@ -367,6 +369,7 @@ vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const u
     a.cfg_in = configs;
     a.hcache = at<float>(ws, w.hcache);
     a.act = at<float>(ws, w.act);
+    a.lgT = at<float>(ws, w.lgT);
     a.hT = at<void>(ws, w.hT);
     a.gT = at<void>(ws, w.gT);
     a.nsp = w.nsp;
@@ -401,6 +404,7 @@ vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, i
     a.phc = at<float>(ws, w.phc);
     a.pre = at<double2>(ws, w.pre);
     a.act = at<float>(ws, w.act);
+    a.lgT = at<float>(ws, w.lgT);
     a.hT = at<void>(ws, w.hT);
     a.gT = at<void>(ws, w.gT);
     a.nsp = w.nsp;

@@ -1,0 +1,471 @@
+// Reverse sweep of the energy gradient (backpropagation through the
+// autoregressive chain, Eq. 1 with the App. A cells) for a tile of samples.
+//
+// With E held constant the gradient is that of
+//   L = sum_s [a_s log P(sigma_s) + b_s phi(sigma_s)],
+//   a_s = w_s Re(E_s - Ebar), b_s = 2 w_s Im(E_s - Ebar).
+// At each order position, last to first:
+//   (a) head deltas: a_s (onehot(sigma) - softmax(l)) (Eq. 3) and
+//       b_s pi softsign'(z_sigma) (Eq. 5);
+//   (b) the gradient on the GLU output g, then the GLU deltas (App. A);
+//   (c) their input gradient [d1 | d2] . [W_1 ; W_2] on MFMA;
+//   (d) the gate deltas of the cell (App. A reversed);
+//   (e) their input gradient delta . B_c on MFMA, routed to the one or two
+//       predecessor positions: carried in registers (the previous position),
+//       or parked per column for the vertical predecessor (2D).
+// All deltas are written transposed [position][feature][sample] for the
+// weight-gradient contraction.  Tiles, waves and weight residency follow the
+// forward engine: bfloat16 up to d_h = 128 keeps the transposed weights in
+// registers (8 waves at 128).
+#include "kernels.h"
+
+namespace vmc {
+
+struct BwdArgs {
+    Dims d;
+    const void *BcT, *BgT;  // [NHB*DH][NCP], [KHB][2*DH]
+    const float *Hd;
+    int64_t ns, nsp;
+    const uint8_t *cfg;
+    const float *act;       // [N][NF*DH][nsp] FP32 gate values and GLU pre-activations
+    const float *lgT;       // [N][4][nsp] logits
+    const float *hcache;    // [N][ns][DH] FP32 hidden states (1D: h_{n-1} of the update-gate term)
+    const double *eloc, *w, *stats;
+    void *dtc, *dtg, *dth;  // transposed deltas: cell [N][NDC][nsp], GLU [N][2DH][nsp], heads [N][4][nsp]
+    float *dcol;            // [grid][Lx][MT][DH]
+};
+
+// Rows per tile and waves per workgroup.  From d_h = 128 on, 8 waves (one or
+// two 16-unit blocks per wave) hold the transposed weights; one such
+// workgroup fills a compute unit, so the tile is sized to spread the usual
+// sample counts over the chip in one round (48 rows at d_h = 128).
+#define BWD_MT(DH) ((DH) == 128 ? 48 : (DH) >= 256 ? 32 : 64)
+#define BWD_NW(DH) ((DH) >= 128 ? 8 : 4)
+
+template <class P, int DIMS, int DH, int NW>
+struct BwdCfg {
+    static constexpr int WU = (DH / 16 < NW) ? DH / 16 : NW;
+    static constexpr int WR = NW / WU;
+    static constexpr int UW = DH / WU;
+    static constexpr int UB = UW / 16;
+    static constexpr int MT = BWD_MT(DH);
+    static constexpr int RW = MT / WR;
+    static constexpr int RB = RW / 16;
+    static constexpr int KS = P::KSTEP;
+    static constexpr int NCP = cround(3 * DH, KS);   // contraction of the cell dX
+    static constexpr int NGK = 2 * DH / KS;         // k-steps of the GLU dX
+    static constexpr int NCK = NCP / KS;            // k-steps of the cell dX
+    static constexpr int NOB = DIMS == 1 ? UB : 2 * UB;  // output blocks of the cell dX (hz, vt)
+    static constexpr int PADE = 16 / (int)sizeof(typename P::store_t);
+    static constexpr int D_LD = NCP + PADE;         // shared row stride of the GLU and cell delta tiles
+};
+
+template <class P, int DIMS, int DH, int NW, int REGW>
+__global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
+    typedef BwdCfg<P, DIMS, DH, NW> C;
+    typedef typename P::store_t T;
+    constexpr int MT = C::MT, RB = C::RB, UB = C::UB, VEC = P::VEC, KS = C::KS;
+    constexpr int NCP = C::NCP, NGK = C::NGK, NCK = C::NCK, NOB = C::NOB, D_LD = C::D_LD, NT = NW * 64;
+    constexpr int NA = DIMS == 1 ? 4 : 3;
+    constexpr int NF = NA + 2;
+    constexpr int NDC = DIMS == 1 ? 4 * DH : 3 * DH;
+
+    __shared__ __align__(16) T sD[MT * D_LD];  // GLU deltas, then cell deltas
+    __shared__ __align__(16) float sDL[MT][4];
+    __shared__ float sCoef[MT][2];
+    __shared__ int sRow[MT];
+    // dynamic LDS: (REGW) the GLU weights BgT [DH][G_LD], then the tile's
+    // configurations [MT][N]
+    extern __shared__ __align__(16) uint8_t sDyn[];
+    constexpr int G_LD = 2 * DH + C::PADE;
+    T *const sBg = (T *)sDyn;
+    uint8_t *const sSig = sDyn + (REGW ? (size_t)DH * G_LD * sizeof(T) : 0);
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w / C::WU, wu = w % C::WU;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int N = a.d.N, Lx = a.d.Lx, Ly = a.d.Ly;
+    const int cplx = a.d.cplx, glu = a.d.glu;
+    const int64_t ns = a.ns, nsp = a.nsp;
+    const T *__restrict__ BcT = (const T *)a.BcT;
+    const T *__restrict__ BgT = (const T *)a.BgT;
+    float *dcol = a.dcol + (int64_t)blockIdx.x * Lx * MT * DH;
+
+    // head weights of this lane's units
+    float hw[4][UB];
+#pragma unroll
+    for (int ub = 0; ub < UB; ub++)
+#pragma unroll
+        for (int o = 0; o < 4; o++) hw[o][ub] = a.Hd[o * DH + wu * C::UW + ub * 16 + l16];
+
+    // REGW: transposed cell weights in registers, GLU weights in LDS
+    uint4 wc[REGW ? NCK : 1][REGW ? NOB : 1];
+    if (REGW) {
+        for (int e = tid; e < DH * (2 * DH / VEC); e += NT) {
+            const int k = e / (2 * DH / VEC), j = (e - k * (2 * DH / VEC)) * VEC;
+            *(uint4 *)&sBg[k * G_LD + j] = *(const uint4 *)&BgT[(int64_t)k * 2 * DH + j];
+        }
+#pragma unroll
+        for (int ks = 0; ks < NCK; ks++)
+#pragma unroll
+            for (int c = 0; c < NOB; c++) {
+                const int k = (c / UB) * DH + wu * C::UW + (c % UB) * 16 + l16;
+                wc[ks][c % NOB] = *(const uint4 *)&BcT[(int64_t)k * NCP + ks * KS + VEC * lq];
+            }
+    }
+
+    const int64_t e0 = (int64_t)blockIdx.x * MT;
+    const int nrow = (int)min((int64_t)MT, ns - e0);
+    if (tid < MT) {
+        const int s = tid < nrow ? (int)(e0 + tid) : -1;
+        sRow[tid] = s;
+        float ca = 0.f, cb = 0.f;
+        if (s >= 0) {
+            const double ws = a.w ? a.w[s] : 1.0 / (double)ns;
+            ca = (float)(ws * (a.eloc[2 * s] - a.stats[0]));
+            cb = (float)(2.0 * ws * (a.eloc[2 * s + 1] - a.stats[1]));
+        }
+        sCoef[tid][0] = ca;
+        sCoef[tid][1] = cb;
+    }
+    for (int e = tid; e < MT * D_LD; e += NT) sD[e] = P::from_float(0.f);
+    __syncthreads();
+    for (int e = tid; e < MT * N; e += NT) {
+        const int r = e / N, c = e - r * N;
+        const int s = sRow[r];
+        sSig[e] = s >= 0 ? a.cfg[(int64_t)s * N + c] : (uint8_t)0;
+    }
+
+    float carry[RB][UB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+        for (int ub = 0; ub < UB; ub++)
+#pragma unroll
+            for (int ii = 0; ii < 4; ii++) carry[rb][ub][ii] = 0.f;
+    __syncthreads();
+
+    // first sample of this lane's 4-row group in row block rb (transposed arrays)
+    auto srow0 = [&](int rb) -> int64_t { return e0 + wr * C::RW + rb * 16 + 4 * lq; };
+    auto feat = [&](int q, int f, int u, int rb) -> float4 {  // 4 samples of one activation feature
+        const int64_t s0 = srow0(rb);
+        if (s0 >= nsp) return make_float4(0.f, 0.f, 0.f, 0.f);
+        return *(const float4 *)&a.act[((int64_t)q * NF * DH + f * DH + u) * nsp + s0];
+    };
+
+    for (int q = N - 1; q >= 0; q--) {
+        const int site = order_site(q, Lx);
+        const int jrow = q / Lx, icol = site - jrow * Lx;
+        const bool row_start = (q % Lx) == 0;
+        const bool last_in_row = ((q + 1) % Lx) == 0;
+        const bool has_vt = DIMS == 2 && jrow > 0;
+        const bool vt_succ_parked = DIMS == 2 && jrow + 1 < Ly && !last_in_row;
+
+        // GLU pre-activations of this step, in flight during the head phase
+        float4 fa1[RB][UB], fa2[RB][UB];
+        if (glu) {
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    const int u = wu * C::UW + ub * 16 + l16;
+                    fa1[rb][ub] = feat(q, NA, u, rb);
+                    fa2[rb][ub] = feat(q, NA + 1, u, rb);
+                }
+        }
+
+        // (a) head deltas
+        if (tid < MT) {
+            const int s = sRow[tid];
+            float d0 = 0.f, d1 = 0.f, z0 = 0.f, z1 = 0.f;
+            if (s >= 0) {
+                const float *lg = a.lgT + (int64_t)q * 4 * nsp + s;
+                const float l0 = lg[0], l1 = lg[nsp];
+                const int sg = sSig[tid * N + site];
+                const float p1 = rcpf_(1.0f + __expf(l0 - l1));  // softmax(l)[1]
+                const float p0 = 1.0f - p1;
+                const float ca = sCoef[tid][0];
+                d0 = ca * ((sg == 0 ? 1.f : 0.f) - p0);
+                d1 = ca * ((sg == 1 ? 1.f : 0.f) - p1);
+                if (cplx) {
+                    const float z = sg ? lg[3 * nsp] : lg[2 * nsp];
+                    const float den = 1.0f + fabsf(z);
+                    const float dz = sCoef[tid][1] * PI_F / (den * den);
+                    if (sg) z1 = dz;
+                    else z0 = dz;
+                }
+            }
+            const int64_t sg_ = e0 + tid;
+            if (sg_ < nsp) {
+                T *dh = (T *)a.dth + (int64_t)q * 4 * nsp + sg_;
+                dh[0] = P::from_float(d0);
+                dh[nsp] = P::from_float(d1);
+                dh[2 * nsp] = P::from_float(z0);
+                dh[3 * nsp] = P::from_float(z1);
+            }
+            *(float4 *)&sDL[tid][0] = make_float4(d0, d1, z0, z1);
+        }
+        __syncthreads();
+
+        // (b) gradient on g; GLU deltas into LDS and the transposed store
+        float dgv[RB][UB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++) {
+#pragma unroll
+            for (int ii = 0; ii < 4; ii++) {
+                const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
+                const float4 dl = *(const float4 *)&sDL[r][0];
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++)
+                    dgv[rb][ub][ii] = hw[0][ub] * dl.x + hw[1][ub] * dl.y + hw[2][ub] * dl.z + hw[3][ub] * dl.w;
+            }
+            if (glu) {
+                const int64_t s0 = srow0(rb);
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    const int u = wu * C::UW + ub * 16 + l16;
+                    float d1[4], d2[4];
+                    const float a1v[4] = {fa1[rb][ub].x, fa1[rb][ub].y, fa1[rb][ub].z, fa1[rb][ub].w};
+                    const float a2v[4] = {fa2[rb][ub].x, fa2[rb][ub].y, fa2[rb][ub].z, fa2[rb][ub].w};
+#pragma unroll
+                    for (int ii = 0; ii < 4; ii++) {
+                        const float sg2 = sigmoidf_(a2v[ii]);
+                        d1[ii] = dgv[rb][ub][ii] * sg2;
+                        d2[ii] = dgv[rb][ub][ii] * a1v[ii] * sg2 * (1.0f - sg2);
+                        const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
+                        sD[r * D_LD + u] = P::from_float(d1[ii]);
+                        sD[r * D_LD + DH + u] = P::from_float(d2[ii]);
+                    }
+                    if (s0 < nsp) {
+                        T *dst = (T *)a.dtg + ((int64_t)q * 2 * DH + u) * nsp + s0;
+                        store4<P>(dst, d1[0], d1[1], d1[2], d1[3]);
+                        store4<P>(dst + (int64_t)DH * nsp, d2[0], d2[1], d2[2], d2[3]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        // (c) GLU input gradient: dh_glu = [d1 | d2] . [W_1 ; W_2] (MFMA)
+        f32x4_t accg[RB][UB];
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+            for (int ub = 0; ub < UB; ub++) accg[rb][ub] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        if (glu) {
+#pragma unroll
+            for (int ks = 0; ks < NGK; ks++) {
+                uint4 af[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++)
+                    af[rb] = *(const uint4 *)&sD[(wr * C::RW + rb * 16 + l16) * D_LD + ks * KS + VEC * lq];
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    uint4 bf;
+                    const int k = wu * C::UW + ub * 16 + l16;
+                    if (REGW) bf = *(const uint4 *)&sBg[k * G_LD + ks * KS + VEC * lq];
+                    else bf = *(const uint4 *)&BgT[(int64_t)k * 2 * DH + ks * KS + VEC * lq];
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++) P::mma(accg[rb][ub], af[rb], bf);
+                }
+            }
+            __syncthreads();  // GLU deltas read before the cell deltas overwrite the tile
+        }
+
+        // gate values of this step
+        float4 fc[NA][RB][UB];
+#pragma unroll
+        for (int f = 0; f < NA; f++)
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) fc[f][rb][ub] = feat(q, f, wu * C::UW + ub * 16 + l16, rb);
+        float4 fhp[DIMS == 1 ? RB : 1][DIMS == 1 ? UB : 1];  // 1D: h_{n-1} (FP32)
+        if (DIMS == 1) {
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    float hv[4] = {0.f, 0.f, 0.f, 0.f};
+                    const int64_t s0 = srow0(rb);
+                    if (q > 0) {
+                        const float *hp = a.hcache + ((int64_t)(q - 1) * ns + s0) * DH + wu * C::UW + ub * 16 + l16;
+#pragma unroll
+                        for (int ii = 0; ii < 4; ii++)
+                            if (s0 + ii < ns) hv[ii] = hp[(int64_t)ii * DH];
+                    }
+                    fhp[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)] = make_float4(hv[0], hv[1], hv[2], hv[3]);
+                }
+        }
+
+        // (d) total dh and the gate deltas
+        float direct[RB][UB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++) {
+            const int64_t s0 = srow0(rb);
+#pragma unroll
+            for (int ub = 0; ub < UB; ub++) {
+                const int u = wu * C::UW + ub * 16 + l16;
+                float gd[4][4];
+                const float4 f0 = fc[0][rb][ub], f1 = fc[1][rb][ub], f2 = fc[2][rb][ub];
+                const float v0[4] = {f0.x, f0.y, f0.z, f0.w}, v1[4] = {f1.x, f1.y, f1.z, f1.w};
+                const float v2[4] = {f2.x, f2.y, f2.z, f2.w};
+                float v3[4] = {0.f, 0.f, 0.f, 0.f}, hp[4] = {0.f, 0.f, 0.f, 0.f};
+                if (DIMS == 1) {
+                    const float4 f3 = fc[NA - 1][rb][ub];
+                    v3[0] = f3.x; v3[1] = f3.y; v3[2] = f3.z; v3[3] = f3.w;
+                    const float4 h4 = fhp[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)];
+                    hp[0] = h4.x; hp[1] = h4.y; hp[2] = h4.z; hp[3] = h4.w;
+                }
+#pragma unroll
+                for (int ii = 0; ii < 4; ii++) {
+                    const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
+                    float dh = (glu ? accg[rb][ub][ii] : dgv[rb][ub][ii]) + carry[rb][ub][ii];
+                    if (vt_succ_parked) dh += dcol[((int64_t)icol * MT + r) * DH + u];
+                    float g0, g1, g2, g3 = 0.f;
+                    if (DIMS == 1) {
+                        // h' = (1-u) h + u c, c = tanh(r m + x-term)
+                        const float uu = v0[ii], rr = v1[ii], m = v2[ii], c = v3[ii];
+                        const float du = dh * (c - hp[ii]), dc = dh * uu;
+                        const float dac = dc * (1.0f - c * c);
+                        g0 = du * uu * (1.0f - uu);
+                        g1 = dac * m * rr * (1.0f - rr);
+                        g2 = dac * rr;
+                        g3 = dac;
+                        direct[rb][ub][ii] = dh * (1.0f - uu);
+                    } else {
+                        // h = u c + (1-u) v
+                        const float c = v0[ii], uu = v1[ii], v = v2[ii];
+                        const float du = dh * (c - v), dc = dh * uu;
+                        g0 = dc * (1.0f - c * c);
+                        g1 = du * uu * (1.0f - uu);
+                        g2 = dh * (1.0f - uu);
+                        direct[rb][ub][ii] = 0.f;
+                    }
+                    gd[0][ii] = g0;
+                    gd[1][ii] = g1;
+                    gd[2][ii] = g2;
+                    gd[3][ii] = g3;
+                    sD[r * D_LD + u] = P::from_float(g0);
+                    sD[r * D_LD + DH + u] = P::from_float(g1);
+                    sD[r * D_LD + 2 * DH + u] = P::from_float(g2);
+                }
+                if (s0 < nsp) {
+#pragma unroll
+                    for (int g = 0; g < (DIMS == 1 ? 4 : 3); g++)
+                        store4<P>((T *)a.dtc + ((int64_t)q * NDC + g * DH + u) * nsp + s0, gd[g][0], gd[g][1],
+                                  gd[g][2], gd[g][3]);
+                }
+            }
+        }
+        __syncthreads();
+
+        // (e) cell input gradient: dA = delta . B_c (MFMA); route to predecessors
+        f32x4_t accx[RB][NOB];
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+            for (int c = 0; c < NOB; c++) accx[rb][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < NCK; ks++) {
+            uint4 af[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++)
+                af[rb] = *(const uint4 *)&sD[(wr * C::RW + rb * 16 + l16) * D_LD + ks * KS + VEC * lq];
+#pragma unroll
+            for (int c = 0; c < NOB; c++) {
+                uint4 bf;
+                if (REGW) {
+                    bf = wc[REGW ? ks : 0][REGW ? c : 0];
+                } else {
+                    const int k = (c / UB) * DH + wu * C::UW + (c % UB) * 16 + l16;
+                    bf = *(const uint4 *)&BcT[(int64_t)k * NCP + ks * KS + VEC * lq];
+                }
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++) P::mma(accx[rb][c], af[rb], bf);
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+            for (int ii = 0; ii < 4; ii++) {
+                const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    const int u = wu * C::UW + ub * 16 + l16;
+                    if (DIMS == 1) {
+                        carry[rb][ub][ii] = accx[rb][ub][ii] + direct[rb][ub][ii];
+                    } else {
+                        const float dhz = accx[rb][ub][ii], dvt = accx[rb][UB + ub][ii];
+                        if (row_start) {
+                            carry[rb][ub][ii] = has_vt ? dvt : 0.f;
+                        } else {
+                            carry[rb][ub][ii] = dhz;
+                            if (has_vt) dcol[((int64_t)icol * MT + r) * DH + u] = dvt;
+                        }
+                    }
+                }
+            }
+        __syncthreads();
+    }
+}
+
+template <class P, int DH>
+struct BwdPick {
+    static constexpr int REGW = (P::VEC == 8 && DH <= 128) ? 1 : 0;
+    static constexpr int NW = BWD_NW(DH);
+};
+
+template <class P, int DIMS, int DH>
+static hipError_t launch_bwd_t(const BwdArgs &a, hipStream_t st) {
+    constexpr int NW = BwdPick<P, DH>::NW, REGW = BwdPick<P, DH>::REGW;
+    typedef BwdCfg<P, DIMS, DH, NW> C;
+    // every column below nsp gets written (zeros past ns)
+    const int grid = (int)((a.nsp + C::MT - 1) / C::MT);
+    size_t dyn = ((size_t)C::MT * a.d.N + 15) / 16 * 16;
+    if (REGW) dyn += (size_t)DH * (2 * DH + C::PADE) * sizeof(typename P::store_t);
+    hipError_t e = hipFuncSetAttribute((const void *)rnn_bwd<P, DIMS, DH, NW, REGW>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((rnn_bwd<P, DIMS, DH, NW, REGW>), dim3(grid), dim3(NW * 64), dyn, st, a);
+    return hipGetLastError();
+}
+
+template <class P, int DIMS>
+static hipError_t launch_bwd_d(const BwdArgs &a, hipStream_t st) {
+    switch (a.d.DH) {
+        case 16: return launch_bwd_t<P, DIMS, 16>(a, st);
+        case 32: return launch_bwd_t<P, DIMS, 32>(a, st);
+        case 64: return launch_bwd_t<P, DIMS, 64>(a, st);
+        case 128: return launch_bwd_t<P, DIMS, 128>(a, st);
+        case 256: return launch_bwd_t<P, DIMS, 256>(a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+int backward_tile_rows(int DH) { return BWD_MT(DH); }
+
+hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st) {
+    BwdArgs a;
+    a.d = b.d;
+    a.BcT = b.BcT;
+    a.BgT = b.BgT;
+    a.Hd = b.Hd;
+    a.ns = b.ns;
+    a.nsp = nsp;
+    a.cfg = b.cfg;
+    a.act = b.act;
+    a.lgT = b.lgT;
+    a.hcache = b.hcache;
+    a.eloc = b.eloc;
+    a.w = b.weights;
+    a.stats = b.stats;
+    a.dtc = b.dtc;
+    a.dtg = b.dtg;
+    a.dth = b.dth;
+    a.dcol = (float *)b.dcol;
+    if (b.d.prec == VMC_BF16) return b.d.dims == 1 ? launch_bwd_d<BF16, 1>(a, st) : launch_bwd_d<BF16, 2>(a, st);
+    return b.d.dims == 1 ? launch_bwd_d<F32, 1>(a, st) : launch_bwd_d<F32, 2>(a, st);
+}
+
+}  // namespace vmc

@@ -100,8 +100,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     const T *__restrict__ Bc = (const T *)a.Bc;
     const T *__restrict__ Bg = (const T *)a.Bg;
     const int64_t ns_c = a.ns_cache;
-    const int NA = nact_per_unit(DIMS);
-    const int AW = act_width(DIMS, DH);
+    constexpr int NA = DIMS == 1 ? 4 : 3;  // gate features; the GLU pair follows
     T *colbuf = (T *)a.colbuf + (int64_t)blockIdx.x * Lx * MT * DH;
     const int l16 = lane & 15, lq = lane >> 4;
 
@@ -394,6 +393,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 return has_vt;
             };
             auto epilogue = [&](int rb, const f32x4_t *acc) {
+                float gvs[STORE ? 4 : 1][UB][4];  // gate values of this block, for the transposed store
 #pragma unroll
                 for (int ii = 0; ii < 4; ii++) {
                     const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
@@ -423,15 +423,13 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                         }
                         hv[rb][ub][ii] = (STORE && s < 0) ? 0.f : h;
                         if (DIMS == 2) sH[cb][r * H_LD + u] = cvt<P>(h);
-                        if (s >= 0) {
-                            if (store_h) a.hcache[((int64_t)q * ns_c + s) * DH + u] = h;
-                            if (store_act) {
-                                float *ar = a.act + ((int64_t)q * ns_c + s) * AW;
-                                ar[u] = s0;
-                                ar[DH + u] = s1;
-                                ar[2 * DH + u] = s2;
-                                if (DIMS == 1) ar[3 * DH + u] = s3;
-                            }
+                        if (s >= 0 && store_h) a.hcache[((int64_t)q * ns_c + s) * DH + u] = h;
+                        if (STORE) {
+                            const bool ok = s >= 0;
+                            gvs[0][ub % UB][ii] = ok ? s0 : 0.f;
+                            gvs[STORE ? 1 : 0][ub % UB][ii] = ok ? s1 : 0.f;
+                            gvs[STORE ? 2 : 0][ub % UB][ii] = ok ? s2 : 0.f;
+                            gvs[STORE ? 3 : 0][ub % UB][ii] = ok ? s3 : 0.f;
                         }
                     }
                 }
@@ -443,6 +441,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                             const int u = wu * C::UW + ub * 16 + l16;
                             store4<P>((T *)a.hT + ((int64_t)q * DH + u) * a.nsp + s0, hv[rb][ub][0], hv[rb][ub][1],
                                       hv[rb][ub][2], hv[rb][ub][3]);
+#pragma unroll
+                            for (int f = 0; f < NA; f++)
+                                *(float4 *)&a.act[((int64_t)q * (NA + 2) * DH + f * DH + u) * a.nsp + s0] =
+                                    make_float4(gvs[STORE ? f : 0][ub][0], gvs[STORE ? f : 0][ub][1],
+                                                gvs[STORE ? f : 0][ub][2], gvs[STORE ? f : 0][ub][3]);
                         }
                     }
                 }
@@ -538,7 +541,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 
             // 4. GLU (MFMA) and heads (FP32)
             auto glu_epilogue = [&](int rb, const f32x4_t *acc2) {
-                float part[4][4], gk[UB][4];
+                float part[4][4], gk[UB][4], ga1[STORE ? UB : 1][4], ga2[STORE ? UB : 1][4];
 #pragma unroll
                 for (int ii = 0; ii < 4; ii++)
 #pragma unroll
@@ -555,15 +558,12 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                             const float a1 = acc2[ub][ii] + gb1[ub];
                             const float a2 = acc2[UB + ub][ii] + gb2[ub];
                             g = a1 * sigmoidf_(a2);
-                            if (store_act && s >= 0) {
-                                float *ar = a.act + ((int64_t)q * ns_c + s) * AW + NA * DH;
-                                ar[u] = a1;
-                                ar[DH + u] = a2;
-                                ar[2 * DH + u] = g;
+                            if (STORE) {
+                                ga1[ub % UB][ii] = s >= 0 ? a1 : 0.f;
+                                ga2[ub % UB][ii] = s >= 0 ? a2 : 0.f;
                             }
                         } else {
                             g = hv[rb][ub][ii];
-                            if (store_act && s >= 0) a.act[((int64_t)q * ns_c + s) * AW + (NA + 2) * DH + u] = g;
                         }
                         part[ii][0] += hw[0][ub] * g;
                         part[ii][1] += hw[1][ub] * g;
@@ -582,6 +582,10 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                             const int u = wu * C::UW + ub * 16 + l16;
                             store4<P>((T *)a.gT + ((int64_t)q * DH + u) * a.nsp + s0, gk[ub][0], gk[ub][1], gk[ub][2],
                                       gk[ub][3]);
+                            float *fa = &a.act[((int64_t)q * (NA + 2) * DH + NA * DH + u) * a.nsp + s0];
+                            *(float4 *)fa = make_float4(ga1[ub % UB][0], ga1[ub % UB][1], ga1[ub % UB][2], ga1[ub % UB][3]);
+                            *(float4 *)(fa + (int64_t)DH * a.nsp) =
+                                make_float4(ga2[ub % UB][0], ga2[ub % UB][1], ga2[ub % UB][2], ga2[ub % UB][3]);
                         }
                     }
                 }
@@ -695,11 +699,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                     a.pre[(int64_t)s * N + q] = make_double2(acc_lp, acc_ph);
                 }
                 if (store_act) {
-                    float *ar = a.act + ((int64_t)q * ns_c + s) * AW + (NA + 3) * DH;
-                    ar[0] = l0;
-                    ar[1] = l1;
-                    ar[2] = z0;
-                    ar[3] = z1;
+                    float *lg = a.lgT + (int64_t)q * 4 * a.nsp + s;
+                    lg[0] = l0;
+                    lg[a.nsp] = l1;
+                    lg[2 * a.nsp] = z0;
+                    lg[3 * a.nsp] = z1;
                 }
             }
             __syncthreads();

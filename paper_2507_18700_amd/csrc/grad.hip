@@ -68,319 +68,6 @@ __global__ __launch_bounds__(1024) void stats_kernel(int64_t ns, const double *e
     }
 }
 
-// ------------------------------------------------------------ reverse sweep
-
-struct BwdArgs {
-    Dims d;
-    const void *BcT, *BgT;
-    const float *E, *Hd;
-    int64_t ns;
-    const uint8_t *cfg;
-    const float *hcache, *act;
-    const double *eloc, *w, *stats;
-    void *dtc, *dtg, *dth;  // transposed deltas: cell [N][NDC][nsp], GLU [N][2DH][nsp], heads [N][4][nsp]
-    int64_t nsp;            // sample stride of the transposed arrays (ns rounded up to 32)
-    float *dcol;            // [grid][Lx][MT][DH]
-};
-
-
-// Reverse sweep over the order positions for a tile of samples.  At each
-// position: head deltas (softmax / softsign derivatives, Eqs. 3, 5), GLU
-// deltas and their input gradient (MFMA), the gate deltas of the cell
-// (App. A) and their input gradient (MFMA), which is routed to the one or two
-// predecessor positions (carried in registers, or parked per column for the
-// vertical predecessor in 2D).
-template <class P, int DIMS, int DH>
-__global__ __launch_bounds__(256) void rnn_backward(BwdArgs a) {
-    typedef FwdCfg<P, DIMS, DH> C;
-    typedef typename P::store_t T;
-    constexpr int MT = C::MT, RB = C::RB, UB = C::UB, NCP = C::NCP, VEC = P::VEC, KSTEP = P::KSTEP;
-    constexpr int PADE = C::PADE;
-    // the GLU deltas (2*DH columns) and the cell deltas (3*DH columns) share
-    // one LDS tile with one row stride; columns >= 3*DH stay zero
-    constexpr int D3_LD = NCP + PADE, D2_LD = D3_LD;
-    constexpr int NA = DIMS == 1 ? 4 : 3;
-    constexpr int NDC = DIMS == 1 ? 4 * DH : 3 * DH;  // stored cell-delta width
-    constexpr int NOB = DIMS == 1 ? UB : 2 * UB;      // output column blocks of the cell dX
-
-    __shared__ __align__(16) T sDb[MT * D3_LD];
-    T *const sD3 = sDb;
-    T *const sD2 = sDb;
-    __shared__ float sDL[MT][4];
-    __shared__ float sCoef[MT][2];
-    __shared__ int sRow[MT];
-    extern __shared__ uint8_t sSig[];
-
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wr = w / C::WU, wu = w % C::WU;
-    const int N = a.d.N, Lx = a.d.Lx, Ly = a.d.Ly;
-    const int cplx = a.d.cplx, glu = a.d.glu;
-    const int64_t ns = a.ns;
-    const int AW = act_width(DIMS, DH);
-    const T *__restrict__ BcT = (const T *)a.BcT;
-    const T *__restrict__ BgT = (const T *)a.BgT;
-    const float *__restrict__ E = a.E;
-    const float *__restrict__ Hd = a.Hd;
-    float *dcol = a.dcol + (int64_t)blockIdx.x * Lx * MT * DH;
-
-    const int64_t e0 = (int64_t)blockIdx.x * MT;
-    const int nrow = (int)min((int64_t)MT, ns - e0);
-    if (tid < MT) {
-        int s = tid < nrow ? (int)(e0 + tid) : -1;
-        sRow[tid] = s;
-        float ca = 0.f, cb = 0.f;
-        if (s >= 0) {
-            const double ws = a.w ? a.w[s] : 1.0 / (double)ns;
-            ca = (float)(ws * (a.eloc[2 * s] - a.stats[0]));
-            cb = (float)(2.0 * ws * (a.eloc[2 * s + 1] - a.stats[1]));
-        }
-        sCoef[tid][0] = ca;
-        sCoef[tid][1] = cb;
-    }
-    for (int e = tid; e < MT * D3_LD; e += blockDim.x) sDb[e] = P::from_float(0.f);
-    __syncthreads();
-    for (int e = tid; e < MT * N; e += blockDim.x) {
-        int r = e / N, c = e - r * N;
-        int s = sRow[r];
-        sSig[e] = s >= 0 ? a.cfg[(int64_t)s * N + c] : (uint8_t)0;
-    }
-
-    float carry[RB][UB][4];
-#pragma unroll
-    for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-        for (int ub = 0; ub < UB; ub++)
-#pragma unroll
-            for (int ii = 0; ii < 4; ii++) carry[rb][ub][ii] = 0.f;
-    __syncthreads();
-
-    for (int q = N - 1; q >= 0; q--) {
-        const int site = order_site(q, Lx);
-        const int jrow = q / Lx, icol = site - jrow * Lx;
-        const bool row_start = (q % Lx) == 0;
-        const bool last_in_row = ((q + 1) % Lx) == 0;
-        const bool has_vt = DIMS == 2 && jrow > 0;
-        const bool vt_succ_parked = DIMS == 2 && jrow + 1 < Ly && !last_in_row;
-
-        // (a) head deltas
-        if (tid < MT) {
-            const int s = sRow[tid];
-            float d0 = 0.f, d1 = 0.f, z0 = 0.f, z1 = 0.f;
-            if (s >= 0) {
-                const float *ar = a.act + ((int64_t)q * ns + s) * AW + (NA + 3) * DH;
-                const float l0 = ar[0], l1 = ar[1];
-                const int sg = sSig[tid * N + site];
-                const float p1 = 1.0f / (1.0f + expf(l0 - l1));  // softmax(l)[1]
-                const float p0 = 1.0f - p1;
-                const float ca = sCoef[tid][0];
-                d0 = ca * ((sg == 0 ? 1.f : 0.f) - p0);
-                d1 = ca * ((sg == 1 ? 1.f : 0.f) - p1);
-                if (cplx) {
-                    const float z = sg ? ar[3] : ar[2];
-                    const float den = 1.0f + fabsf(z);
-                    const float dz = sCoef[tid][1] * PI_F / (den * den);
-                    if (sg) z1 = dz;
-                    else z0 = dz;
-                }
-            }
-            const int64_t sg_ = e0 + tid;
-            if (sg_ < a.nsp) {
-                T *dh = (T *)a.dth + (int64_t)q * 4 * a.nsp + sg_;
-                dh[0] = P::from_float(d0);
-                dh[a.nsp] = P::from_float(d1);
-                dh[2 * a.nsp] = P::from_float(z0);
-                dh[3 * a.nsp] = P::from_float(z1);
-            }
-            sDL[tid][0] = d0;
-            sDL[tid][1] = d1;
-            sDL[tid][2] = z0;
-            sDL[tid][3] = z1;
-        }
-        __syncthreads();
-
-        // (b) head -> g, GLU deltas
-        float dgv[RB][UB][4], gd1[RB][UB][4], gd2[RB][UB][4];
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-            for (int ii = 0; ii < 4; ii++) {
-                const int r = wr * C::RW + rb * 16 + 4 * (lane >> 4) + ii;
-                const int s = sRow[r];
-#pragma unroll
-                for (int ub = 0; ub < UB; ub++) {
-                    const int u = wu * C::UW + ub * 16 + (lane & 15);
-                    float dg = Hd[u] * sDL[r][0] + Hd[DH + u] * sDL[r][1] + Hd[2 * DH + u] * sDL[r][2] +
-                               Hd[3 * DH + u] * sDL[r][3];
-                    dgv[rb][ub][ii] = dg;
-                    if (glu) {
-                        float d1 = 0.f, d2 = 0.f;
-                        if (s >= 0) {
-                            const float *ar = a.act + ((int64_t)q * ns + s) * AW + NA * DH;
-                            const float a1 = ar[u], a2 = ar[DH + u];
-                            const float sg2 = sigmoidf_(a2);
-                            d1 = dg * sg2;
-                            d2 = dg * a1 * sg2 * (1.0f - sg2);
-                        }
-                        gd1[rb][ub][ii] = d1;
-                        gd2[rb][ub][ii] = d2;
-                        sD2[r * D2_LD + u] = P::from_float(d1);
-                        sD2[r * D2_LD + DH + u] = P::from_float(d2);
-                    }
-                }
-            }
-        if (glu) {
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++) {
-                const int64_t s0 = e0 + wr * C::RW + rb * 16 + 4 * (lane >> 4);
-                if (s0 >= a.nsp) continue;
-#pragma unroll
-                for (int ub = 0; ub < UB; ub++) {
-                    const int u = wu * C::UW + ub * 16 + (lane & 15);
-                    T *dst = (T *)a.dtg + ((int64_t)q * 2 * DH + u) * a.nsp + s0;
-                    store4<P>(dst, gd1[rb][ub][0], gd1[rb][ub][1], gd1[rb][ub][2], gd1[rb][ub][3]);
-                    store4<P>(dst + (int64_t)DH * a.nsp, gd2[rb][ub][0], gd2[rb][ub][1], gd2[rb][ub][2],
-                              gd2[rb][ub][3]);
-                }
-            }
-        }
-        __syncthreads();
-
-        // (c) GLU input gradient: dh_glu = [d1 | d2] . [W_1 ; W_2]  (MFMA)
-        f32x4_t accg[RB][UB];
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-            for (int ub = 0; ub < UB; ub++) accg[rb][ub] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-        if (glu) {
-#pragma unroll 2
-            for (int kk = 0; kk < 2 * DH; kk += KSTEP) {
-                uint4 af[RB];
-#pragma unroll
-                for (int rb = 0; rb < RB; rb++) {
-                    int row = wr * C::RW + rb * 16 + (lane & 15);
-                    af[rb] = *(const uint4 *)&sD2[row * D2_LD + kk + VEC * (lane >> 4)];
-                }
-#pragma unroll
-                for (int ub = 0; ub < UB; ub++) {
-                    int k = wu * C::UW + ub * 16 + (lane & 15);
-                    uint4 bf = *(const uint4 *)&BgT[(int64_t)k * 2 * DH + kk + VEC * (lane >> 4)];
-#pragma unroll
-                    for (int rb = 0; rb < RB; rb++) P::mma(accg[rb][ub], af[rb], bf);
-                }
-            }
-        }
-
-        __syncthreads();  // the GLU deltas are read before the cell deltas overwrite them
-
-        // (d) total dh and the cell deltas (App. A gate algebra, reversed)
-        float direct[RB][UB][4];  // 1D: dh (1-u), the gradient reaching h_{n-1} directly
-        float cg[4][RB][UB][4];   // cell deltas per gate, kept for the transposed store
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-            for (int ii = 0; ii < 4; ii++) {
-                const int r = wr * C::RW + rb * 16 + 4 * (lane >> 4) + ii;
-                const int s = sRow[r];
-#pragma unroll
-                for (int ub = 0; ub < UB; ub++) {
-                    const int u = wu * C::UW + ub * 16 + (lane & 15);
-                    float dh = (glu ? accg[rb][ub][ii] : dgv[rb][ub][ii]) + carry[rb][ub][ii];
-                    if (vt_succ_parked) dh += dcol[((int64_t)icol * MT + r) * DH + u];
-                    float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
-                    direct[rb][ub][ii] = 0.f;
-                    if (s >= 0) {
-                        const float *ar = a.act + ((int64_t)q * ns + s) * AW;
-                        if (DIMS == 1) {
-                            const float uu = ar[u], rr = ar[DH + u], m = ar[2 * DH + u], c = ar[3 * DH + u];
-                            const float hp = q > 0 ? a.hcache[((int64_t)(q - 1) * ns + s) * DH + u] : 0.f;
-                            const float du = dh * (c - hp), dc = dh * uu;
-                            const float dac = dc * (1.0f - c * c);
-                            g0 = du * uu * (1.0f - uu);     // pre-activation of u
-                            g1 = dac * m * rr * (1.0f - rr); // pre-activation of r
-                            g2 = dac * rr;                  // W_h h + b_h
-                            g3 = dac;                       // candidate pre-activation
-                            direct[rb][ub][ii] = dh * (1.0f - uu);
-                        } else {
-                            const float c = ar[u], uu = ar[DH + u], v = ar[2 * DH + u];
-                            const float du = dh * (c - v), dc = dh * uu;
-                            g0 = dc * (1.0f - c * c);       // candidate pre-activation
-                            g1 = du * uu * (1.0f - uu);     // update-gate pre-activation
-                            g2 = dh * (1.0f - uu);          // U h'
-                        }
-                    }
-                    cg[0][rb][ub][ii] = g0;
-                    cg[1][rb][ub][ii] = g1;
-                    cg[2][rb][ub][ii] = g2;
-                    cg[3][rb][ub][ii] = g3;
-                    sD3[r * D3_LD + u] = P::from_float(g0);
-                    sD3[r * D3_LD + DH + u] = P::from_float(g1);
-                    sD3[r * D3_LD + 2 * DH + u] = P::from_float(g2);
-                }
-            }
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++) {
-            const int64_t s0 = e0 + wr * C::RW + rb * 16 + 4 * (lane >> 4);
-            if (s0 >= a.nsp) continue;
-#pragma unroll
-            for (int ub = 0; ub < UB; ub++) {
-                const int u = wu * C::UW + ub * 16 + (lane & 15);
-#pragma unroll
-                for (int g = 0; g < (DIMS == 1 ? 4 : 3); g++) {
-                    T *dst = (T *)a.dtc + ((int64_t)q * NDC + g * DH + u) * a.nsp + s0;
-                    store4<P>(dst, cg[g][rb][ub][0], cg[g][rb][ub][1], cg[g][rb][ub][2], cg[g][rb][ub][3]);
-                }
-            }
-        }
-        __syncthreads();
-
-        // (e) cell input gradient: dA = delta . B_c  (MFMA); route to predecessors
-        f32x4_t accx[RB][NOB];
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-            for (int c = 0; c < NOB; c++) accx[rb][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-        for (int kk = 0; kk < NCP; kk += KSTEP) {
-            uint4 af[RB];
-#pragma unroll
-            for (int rb = 0; rb < RB; rb++) {
-                int row = wr * C::RW + rb * 16 + (lane & 15);
-                af[rb] = *(const uint4 *)&sD3[row * D3_LD + kk + VEC * (lane >> 4)];
-            }
-#pragma unroll
-            for (int c = 0; c < NOB; c++) {
-                const int half = c / UB, ub = c % UB;
-                const int k = half * DH + wu * C::UW + ub * 16 + (lane & 15);
-                uint4 bf = *(const uint4 *)&BcT[(int64_t)k * NCP + kk + VEC * (lane >> 4)];
-#pragma unroll
-                for (int rb = 0; rb < RB; rb++) P::mma(accx[rb][c], af[rb], bf);
-            }
-        }
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-            for (int ii = 0; ii < 4; ii++) {
-                const int r = wr * C::RW + rb * 16 + 4 * (lane >> 4) + ii;
-#pragma unroll
-                for (int ub = 0; ub < UB; ub++) {
-                    const int u = wu * C::UW + ub * 16 + (lane & 15);
-                    if (DIMS == 1) {
-                        carry[rb][ub][ii] = accx[rb][ub][ii] + direct[rb][ub][ii];
-                    } else {
-                        const float dhz = accx[rb][ub][ii], dvt = accx[rb][UB + ub][ii];
-                        if (row_start) {
-                            carry[rb][ub][ii] = has_vt ? dvt : 0.f;
-                        } else {
-                            carry[rb][ub][ii] = dhz;
-                            if (has_vt) dcol[((int64_t)icol * MT + r) * DH + u] = dvt;
-                        }
-                    }
-                }
-            }
-        __syncthreads();
-    }
-}
-
 // ------------------------------------------------- weight-gradient contraction
 
 struct DwArgs {
@@ -612,65 +299,18 @@ void grad_sizes(const Dims &d, int64_t ns, size_t *part_floats) {
     *part_floats = (size_t)d.N * mx;
 }
 
-template <class P, int DIMS, int DH>
-static hipError_t launch_bwd_t(const BwdArgs &a, int grid, hipStream_t st) {
-    typedef FwdCfg<P, DIMS, DH> C;
-    size_t dyn = ((size_t)C::MT * a.d.N + 15) / 16 * 16;
-    hipError_t e = hipFuncSetAttribute((const void *)rnn_backward<P, DIMS, DH>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rnn_backward<P, DIMS, DH>), dim3(grid), dim3(256), dyn, st, a);
-    return hipGetLastError();
-}
-
-template <class P, int DIMS>
-static hipError_t launch_bwd_d(const BwdArgs &a, int grid, hipStream_t st) {
-    switch (a.d.DH) {
-        case 16: return launch_bwd_t<P, DIMS, 16>(a, grid, st);
-        case 32: return launch_bwd_t<P, DIMS, 32>(a, grid, st);
-        case 64: return launch_bwd_t<P, DIMS, 64>(a, grid, st);
-        case 128: return launch_bwd_t<P, DIMS, 128>(a, grid, st);
-        case 256: return launch_bwd_t<P, DIMS, 256>(a, grid, st);
-    }
-    return hipErrorInvalidValue;
-}
-
 template <class P>
 static void launch_dw_p(const DwArgs &a, const SegDims &sd, hipStream_t st) {
     dim3 grd(sd.Mp / DW_TILE, sd.Kp / DW_TILE, a.d.N);
     hipLaunchKernelGGL(dw_mfma<P>, grd, dim3(256), 0, st, a);
 }
 
-int forward_tile_rows(int DH);
+hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st);
 
 hipError_t launch_grad(const GradBufs &b, hipStream_t st) {
     const Dims &d = b.d;
     hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(1024), 0, st, b.ns, b.eloc, b.weights, b.stats);
-    BwdArgs bw;
-    bw.d = d;
-    bw.BcT = b.BcT;
-    bw.BgT = b.BgT;
-    bw.E = b.E;
-    bw.Hd = b.Hd;
-    bw.ns = b.ns;
-    bw.cfg = b.cfg;
-    bw.hcache = b.hcache;
-    bw.act = b.act;
-    bw.eloc = b.eloc;
-    bw.w = b.weights;
-    bw.stats = b.stats;
-    bw.dtc = b.dtc;
-    bw.dtg = b.dtg;
-    bw.dth = b.dth;
-    bw.nsp = grad_nsp(b.ns);
-    bw.dcol = (float *)b.dcol;
-    const int MT = forward_tile_rows(d.DH);
-    const int grid = (int)((b.ns + MT - 1) / MT);
-    hipError_t e;
-    if (d.prec == VMC_BF16)
-        e = d.dims == 1 ? launch_bwd_d<BF16, 1>(bw, grid, st) : launch_bwd_d<BF16, 2>(bw, grid, st);
-    else
-        e = d.dims == 1 ? launch_bwd_d<F32, 1>(bw, grid, st) : launch_bwd_d<F32, 2>(bw, grid, st);
+    hipError_t e = launch_backward(b, grad_nsp(b.ns), st);
     if (e != hipSuccess) return e;
     {
         const int64_t nsp = grad_nsp(b.ns), tot = (int64_t)d.N * nsp;

@@ -22,7 +22,8 @@ struct FwdArgs {
     float *hcache;           // [N][ns][DH] fp32 hidden states
     float *lpc, *phc;        // [ns][N][2] log-conditionals, phase conditionals
     double2 *pre;            // [ns][N] running (log P, phase) after each position, FP64
-    float *act;              // [N][ns][NACT*DH] activations for the backward
+    float *act;              // [N][NF*DH][nsp] gate and GLU pre-activations for the backward (FP32)
+    float *lgT;              // [N][4][nsp] logits (l0, l1, z0, z1) for the backward
     void *hT, *gT;           // with act: transposed h and GLU output [N][DH][nsp] (store_t)
     int64_t nsp;             // sample stride of the transposed arrays
     int64_t ns_cache;        // row count of the cache arrays
@@ -46,7 +47,7 @@ struct GradBufs {
     const float *E, *Hd;
     int64_t ns;
     const uint8_t *cfg;
-    const float *hcache, *act;
+    const float *hcache, *act, *lgT;
     const double *eloc, *weights;
     double *stats;
     void *dtc, *dtg, *dth;  // transposed deltas (cell, GLU, heads)
@@ -99,8 +100,9 @@ struct FwdCfg {
     static constexpr int NCP = cround(3 * DH, P::KSTEP);      // padded cell-delta width (backward)
 };
 
-// Row width of the activation store (floats): gates, GLU a1, a2, g, 4 logits.
-__host__ __device__ inline int act_width(int dims, int DH) { return (nact_per_unit(dims) + 3) * DH + 4; }
+// Transposed activation features per unit: the gate values (1D: u, r, m, c;
+// 2D: c, u, v) followed by the GLU pre-activations a1, a2.
+__host__ __device__ inline int act_feats(int dims) { return nact_per_unit(dims) + 2; }
 
 
 // bonds of the open chain / square lattice in the order used everywhere:
