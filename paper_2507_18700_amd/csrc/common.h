@@ -11,6 +11,13 @@ namespace vmc {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// two floats to packed bfloat16 (round to nearest even), one v_cvt_pk_bf16_f32
+__device__ inline uint32_t pack_bf16x2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
+}
 
 constexpr int WAVE = 64;
 constexpr float PI_F = 3.14159265358979323846f;
@@ -67,8 +74,12 @@ struct BF16 {
 // reciprocal (v_rcp_f32, 1 ulp); tanh via 2*sigmoid(2x) - 1, whose absolute
 // error stays at float rounding level.
 __device__ inline float rcpf_(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ inline float sigmoidf_(float x) { return rcpf_(1.0f + __expf(-x)); }
-__device__ inline float tanhf_(float x) { return 2.0f * rcpf_(1.0f + __expf(-2.0f * x)) - 1.0f; }
+__device__ inline float sigmoidf_(float x) {
+    return rcpf_(1.0f + __builtin_amdgcn_exp2f(x * -1.4426950408889634f));  // -log2(e)
+}
+__device__ inline float tanhf_(float x) {
+    return 2.0f * rcpf_(1.0f + __builtin_amdgcn_exp2f(x * -2.8853900817779268f)) - 1.0f;  // -2 log2(e)
+}
 __device__ inline float softsignf_(float x) { return x / (1.0f + fabsf(x)); }
 
 // ------------------------------------------------------------------- Philox

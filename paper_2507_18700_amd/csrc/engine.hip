@@ -14,13 +14,15 @@
 //      the MFMA output (biases as per-lane constants);
 //   3. the optional GLU contraction on MFMA;
 //   4. the 2- or 4-logit heads (Eqs. 3, 5) in FP32 as lane partial dot
-//      products, DPP row sums and a cross-wave sum in LDS;
+//      products, a sum over the lane groups and a cross-wave sum in LDS;
 //   5. a per-row finalisation: log-softmax, the sampling decision or the
 //      teacher-forced spin, FP64 accumulation of log P and the phase.
 // The hidden state is double-buffered in LDS (the previous h is the operand
 // while the new h is written), so no operand copies are made.  With REGW the
-// cell weights stay in registers for the whole persistent launch and the GLU
-// weights in LDS; otherwise both stream from L2.
+// cell and GLU weights stay in registers for the whole persistent launch;
+// otherwise both stream from L2.  The weights are the MFMA A operand, so each
+// lane owns 4 consecutive units of one row: the new h goes to LDS as one
+// 8-byte store and a head sum needs only the four lane groups of a row.
 #include <type_traits>
 
 #include "kernels.h"
@@ -47,21 +49,16 @@ struct Eng {
     static constexpr int X_LD = KS + PADE;                     // row stride of the indicator tile
 };
 
-// Sum over the 16 lanes of a DPP row; every lane of the row gets the sum.
-// Each stage is one v_add_f32 with a DPP source (quad swaps, then the half-
-// row and row mirrors).  A DPP read of a VGPR written by the previous VALU
-// instruction needs two wait states, hence the s_nop before each stage.
-__device__ inline float row16_sum(float v) {
-    float t;
-    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
-                 : "=&v"(t) : "v"(v));
-    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
-                 : "=&v"(v) : "v"(t));
-    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_half_mirror row_mask:0xf bank_mask:0xf"
-                 : "=&v"(t) : "v"(v));
-    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_mirror row_mask:0xf bank_mask:0xf"
-                 : "=&v"(v) : "v"(t));
-    return v;
+// Sum over the four 16-lane groups of a wave (lanes l, l^16, l^32, l^48);
+// every lane gets the sum, with the same bits in all four lanes.  Two
+// cross-row swaps (v_permlane16_swap, v_permlane32_swap) and two adds.
+__device__ inline float group4_sum(float v) {
+    const uint32_t b = __float_as_uint(v);
+    const auto x = __builtin_amdgcn_permlane16_swap(b, b, false, false);
+    const float s = __uint_as_float(x[0]) + __uint_as_float(x[1]);
+    const uint32_t c = __float_as_uint(s);
+    const auto y = __builtin_amdgcn_permlane32_swap(c, c, false, false);
+    return __uint_as_float(y[0]) + __uint_as_float(y[1]);
 }
 
 template <class P>
@@ -70,6 +67,18 @@ template <>
 __device__ inline float cvt<F32>(float x) { return x; }
 template <>
 __device__ inline uint16_t cvt<BF16>(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+
+// Four consecutive units of one row into an operand tile (one 8- or 16-byte store).
+template <class P>
+__device__ inline void put4(typename P::store_t *dst, const float *v);
+template <>
+__device__ inline void put4<F32>(float *dst, const float *v) {
+    *(float4 *)dst = make_float4(v[0], v[1], v[2], v[3]);
+}
+template <>
+__device__ inline void put4<BF16>(uint16_t *dst, const float *v) {
+    *(uint2 *)dst = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+}
 
 template <class P, int DIMS, int DH, int NW, int REGW, int STORE>
 __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int store_h_, int store_lpc_,
@@ -81,13 +90,13 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     constexpr int MT = C::MT, RB = C::RB, UB = C::UB, KS = C::KS, VEC = P::VEC;
     constexpr int KHB = C::KHB, NKB = C::NKB, NKS = C::NKS, KPX = C::KPX;
     constexpr int H_LD = C::H_LD, X_LD = C::X_LD, NT = NW * 64;
-    constexpr int GLD = KHB + C::PADE;  // row stride of the GLU weights in LDS
+    constexpr int NKG = KHB / KS;  // k-steps of the GLU contraction
 
     __shared__ __align__(16) T sH[2][MT * H_LD];
     __shared__ __align__(16) T sV[DIMS == 2 ? MT * H_LD : 8];
     __shared__ __align__(16) T sX[MT * X_LD];
-    __shared__ __align__(16) T sG[REGW ? 2 * DH * GLD : 8];
-    __shared__ float sLog[C::WU][MT][4];
+    __shared__ __align__(16) float sLog[C::WU][MT][4];
+    __shared__ __align__(16) float sHw[2][DH];  // phase-head rows (complex amplitudes)
     __shared__ int sRow[MT];
     __shared__ int sTile;
     extern __shared__ uint8_t sSig[];  // [MT][N]
@@ -96,41 +105,41 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     const int wr = w / C::WU, wu = w % C::WU;
     const int N = a.d.N, Lx = a.d.Lx, Ly = a.d.Ly;
     const int cplx = a.d.cplx, glu = a.d.glu;
-    const int NO = cplx ? 4 : 2;
     const T *__restrict__ Bc = (const T *)a.Bc;
     const T *__restrict__ Bg = (const T *)a.Bg;
     const int64_t ns_c = a.ns_cache;
     constexpr int NA = DIMS == 1 ? 4 : 3;  // gate features; the GLU pair follows
     T *colbuf = (T *)a.colbuf + (int64_t)blockIdx.x * Lx * MT * DH;
     const int l16 = lane & 15, lq = lane >> 4;
+    // The MFMAs run with the weights as the A operand, so a lane's outputs
+    // are 4 consecutive hidden units (4*lq + i of a 16-unit block) of one
+    // row (l16 of a 16-row block).
+    auto unit0 = [&](int ub) { return wu * C::UW + ub * 16 + 4 * lq; };
 
-    // per-lane constants: biases, head weights (fixed unit per lane and block)
-    float bias0[UB], bias1[UB], bias2[UB], bin_[UB], win0[UB], win1[UB], gb1[UB], gb2[UB], hw[4][UB];
+    // per-lane constants of this lane's units: GLU biases, amplitude head
+    float gb1[UB][4], gb2[UB][4], hw0[UB][4], hw1[UB][4];
+    float bin_[DIMS == 1 ? UB : 1][4], win0[DIMS == 1 ? UB : 1][4], win1[DIMS == 1 ? UB : 1][4];
 #pragma unroll
-    for (int ub = 0; ub < UB; ub++) {
-        const int u = wu * C::UW + ub * 16 + l16;
-        if (DIMS == 1) {
-            bias0[ub] = a.E[E1_BG * DH + u];
-            bias1[ub] = a.E[E1_BR * DH + u];
-            bias2[ub] = a.E[E1_BH * DH + u];
-            bin_[ub] = a.E[E1_BIN * DH + u];
-            win0[ub] = a.E[E1_XIN0 * DH + u];
-            win1[ub] = a.E[E1_XIN1 * DH + u];
-        } else {
-            bias0[ub] = a.E[E2_B * DH + u];
-            bias1[ub] = a.E[E2_BG * DH + u];
-            bias2[ub] = 0.f;
-            bin_[ub] = win0[ub] = win1[ub] = 0.f;
+    for (int ub = 0; ub < UB; ub++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int u = unit0(ub) + i;
+            gb1[ub][i] = a.E[E_B1 * DH + u];
+            gb2[ub][i] = a.E[E_B2 * DH + u];
+            hw0[ub][i] = a.Hd[u];
+            hw1[ub][i] = a.Hd[DH + u];
+            if (DIMS == 1) {
+                bin_[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_BIN * DH + u];
+                win0[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_XIN0 * DH + u];
+                win1[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_XIN1 * DH + u];
+            }
         }
-        gb1[ub] = a.E[E_B1 * DH + u];
-        gb2[ub] = a.E[E_B2 * DH + u];
-#pragma unroll
-        for (int o = 0; o < 4; o++) hw[o][ub] = a.Hd[o * DH + u];
-    }
+    for (int e = tid; e < 2 * DH; e += NT) (&sHw[0][0])[e] = a.Hd[2 * DH + e];
     const float hc0 = a.hc[0], hc1 = a.hc[1], hc2 = a.hc[2], hc3 = a.hc[3];
 
-    // cell weights in registers (REGW): fragment of gate g, k-step ks, unit block ub
+    // REGW: cell and GLU weight fragments in registers for the whole launch
     uint4 wreg[REGW ? 3 : 1][REGW ? NKS : 1][REGW ? UB : 1];
+    uint4 wgl[REGW ? 2 : 1][REGW ? NKG : 1][REGW ? UB : 1];
     if (REGW) {
 #pragma unroll
         for (int g = 0; g < 3; g++)
@@ -141,18 +150,52 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                     const int n = g * DH + wu * C::UW + ub * 16 + l16;
                     wreg[g][ks][ub] = *(const uint4 *)&Bc[(int64_t)n * KPX + ks * KS + VEC * lq];
                 }
-        // GLU weights into LDS
-        for (int e = tid; e < 2 * DH * (KHB / VEC); e += NT) {
-            const int n = e / (KHB / VEC), c = (e % (KHB / VEC)) * VEC;
-            *(uint4 *)&sG[n * GLD + c] = *(const uint4 *)&Bg[(int64_t)n * KHB + c];
-        }
+#pragma unroll
+        for (int g = 0; g < 2; g++)
+#pragma unroll
+            for (int kq = 0; kq < NKG; kq++)
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    const int n = g * DH + wu * C::UW + ub * 16 + l16;
+                    wgl[g][kq][ub] = *(const uint4 *)&Bg[(int64_t)n * KHB + kq * KS + VEC * lq];
+                }
     }
-    // zero the operand tiles once (padding columns stay zero)
+    // zero the operand tiles once (padding columns stay zero); the bias
+    // class of the indicator block is always on
     for (int e = tid; e < 2 * MT * H_LD; e += NT) (&sH[0][0])[e] = cvt<P>(0.f);
     if (DIMS == 2)
         for (int e = tid; e < MT * H_LD; e += NT) sV[e] = cvt<P>(0.f);
-    for (int e = tid; e < MT * X_LD; e += NT) sX[e] = cvt<P>(0.f);
+    for (int e = tid; e < MT * X_LD; e += NT) {
+        const int c = e % X_LD;
+        const bool bias_col = VEC == 8 ? (c == 8 || c == 9) : c == 4;
+        sX[e] = cvt<P>(bias_col ? 1.f : 0.f);
+    }
 
+    // Head outputs of one 16-row block: sum the lane partials over the four
+    // lane groups of a row, then one lane group stores the wave's sums.
+    auto head_out = [&](int r, float p0, float p1, float p2, float p3) {
+        p0 = group4_sum(p0);
+        p1 = group4_sum(p1);
+        if (cplx) {
+            p2 = group4_sum(p2);
+            p3 = group4_sum(p3);
+        }
+        if (lq == 0) *(float4 *)&sLog[wu][r][0] = make_float4(p0, p1, p2, p3);
+    };
+    // partial head sums of the lane's 4 units of row r for g (4 values per block)
+    auto head_part = [&](int ub, const float *g, float &p0, float &p1, float &p2, float &p3) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            p0 += hw0[ub][i] * g[i];
+            p1 += hw1[ub][i] * g[i];
+        }
+        if (cplx) {
+            const float4 z0 = *(const float4 *)&sHw[0][unit0(ub)];
+            const float4 z1 = *(const float4 *)&sHw[1][unit0(ub)];
+            p2 += z0.x * g[0] + z0.y * g[1] + z0.z * g[2] + z0.w * g[3];
+            p3 += z1.x * g[0] + z1.y * g[1] + z1.z * g[2] + z1.w * g[3];
+        }
+    };
     bool first = true;
     for (;;) {
         // ---------------------------------------------------------- tile
@@ -218,7 +261,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 #pragma unroll
             for (int ub = 0; ub < (DIMS == 1 ? UB : 1); ub++)
 #pragma unroll
-                for (int ii = 0; ii < 4; ii++) hreg[rb][ub][ii] = 0.f;
+                for (int i = 0; i < 4; i++) hreg[rb][ub][i] = 0.f;
         if (p >= 0) {
             const int pb = ((p + 1) & 1) ^ 1;
             for (int e = tid; e < MT * (DH / 4); e += NT) {
@@ -226,25 +269,24 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 const int s = sRow[r];
                 float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (s >= 0) v = *(const float4 *)&a.hcache[((int64_t)p * ns_c + s) * DH + c];
-                T *d = &sH[pb][r * H_LD + c];
-                d[0] = cvt<P>(v.x);
-                d[1] = cvt<P>(v.y);
-                d[2] = cvt<P>(v.z);
-                d[3] = cvt<P>(v.w);
+                const float vv[4] = {v.x, v.y, v.z, v.w};
+                put4<P>(&sH[pb][r * H_LD + c], vv);
             }
             if (DIMS == 1) {
 #pragma unroll
-                for (int rb = 0; rb < RB; rb++)
+                for (int rb = 0; rb < RB; rb++) {
+                    const int s = sRow[wr * C::RW + rb * 16 + l16];
 #pragma unroll
-                    for (int ub = 0; ub < UB; ub++)
-#pragma unroll
-                        for (int ii = 0; ii < 4; ii++) {
-                            const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
-                            const int u = wu * C::UW + ub * 16 + l16;
-                            const int s = sRow[r];
-                            hreg[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)][ii] =
-                                s >= 0 ? a.hcache[((int64_t)p * ns_c + s) * DH + u] : 0.f;
-                        }
+                    for (int ub = 0; ub < UB; ub++) {
+                        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (s >= 0) v = *(const float4 *)&a.hcache[((int64_t)p * ns_c + s) * DH + unit0(ub)];
+                        float *hr = hreg[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)];
+                        hr[0] = v.x;
+                        hr[1] = v.y;
+                        hr[2] = v.z;
+                        hr[3] = v.w;
+                    }
+                }
             }
         }
         double acc_lp = 0.0, acc_ph = 0.0;
@@ -300,15 +342,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
                 T *d = &sV[r * H_LD + c];
                 if (src == 1) {
-                    d[0] = cvt<P>(pfa[i].x);
-                    d[1] = cvt<P>(pfa[i].y);
-                    d[2] = cvt<P>(pfa[i].z);
-                    d[3] = cvt<P>(pfa[i].w);
+                    const float va[4] = {pfa[i].x, pfa[i].y, pfa[i].z, pfa[i].w};
+                    put4<P>(d, va);
                     if (VEC == 8) {
-                        d[4] = cvt<P>(pfb[i].x);
-                        d[5] = cvt<P>(pfb[i].y);
-                        d[6] = cvt<P>(pfb[i].z);
-                        d[7] = cvt<P>(pfb[i].w);
+                        const float vb[4] = {pfb[i].x, pfb[i].y, pfb[i].z, pfb[i].w};
+                        put4<P>(d + 4, vb);
                     }
                 } else {
                     *(uint4 *)d = __builtin_bit_cast(uint4, pfa[i]);
@@ -339,11 +377,9 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                             const float *src = &a.hcache[((int64_t)pos_vt * ns_c + s) * DH + c];
 #pragma unroll
                             for (int x = 0; x < VEC; x += 4) {
-                                float4 v = *(const float4 *)&src[x];
-                                d[x] = cvt<P>(v.x);
-                                d[x + 1] = cvt<P>(v.y);
-                                d[x + 2] = cvt<P>(v.z);
-                                d[x + 3] = cvt<P>(v.w);
+                                const float4 v = *(const float4 *)&src[x];
+                                const float vv[4] = {v.x, v.y, v.z, v.w};
+                                put4<P>(d + x, vv);
                             }
                         } else {
                             *(uint4 *)d = make_uint4(0, 0, 0, 0);
@@ -376,7 +412,6 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             // block at a time, so that the epilogue of one block runs under
             // the MFMAs of the next; with streamed weights all row blocks per
             // weight fragment (each fragment loaded once per step).
-            float hv[RB][UB][4];
             auto a_frag = [&](int rb, int ks) -> uint4 {
                 const int blk = ks / NKB;
                 const bool is_x = ks == NKS - 1;
@@ -393,62 +428,64 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 return has_vt;
             };
             auto epilogue = [&](int rb, const f32x4_t *acc) {
-                float gvs[STORE ? 4 : 1][UB][4];  // gate values of this block, for the transposed store
+                const int r = wr * C::RW + rb * 16 + l16;
+                const int s = sRow[r];
+                int xz = 0;
+                if (DIMS == 1) xz = has_hz ? sSig[r * N + site_hz] : -1;
+                float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
 #pragma unroll
-                for (int ii = 0; ii < 4; ii++) {
-                    const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
-                    const int s = sRow[r];
-                    int xz = 0;
-                    if (DIMS == 1) xz = has_hz ? sSig[r * N + site_hz] : -1;
+                for (int ub = 0; ub < UB; ub++) {
+                    const int u0 = unit0(ub);
+                    float hq[4], gv[STORE ? 4 : 1][4];
 #pragma unroll
-                    for (int ub = 0; ub < UB; ub++) {
-                        const int u = wu * C::UW + ub * 16 + l16;
-                        const float g0 = acc[ub][ii], g1 = acc[UB + ub][ii], g2 = acc[2 * UB + ub][ii];
+                    for (int i = 0; i < 4; i++) {
+                        const float g0 = acc[ub][i], g1 = acc[UB + ub][i], g2 = acc[2 * UB + ub][i];
                         float h, s0, s1, s2, s3 = 0.f;
                         if (DIMS == 1) {
-                            const float uu = sigmoidf_(g0 + bias0[ub]);
-                            const float rr = sigmoidf_(g1 + bias1[ub]);
-                            const float m = g2 + bias2[ub];
-                            const float cin = bin_[ub] + (xz == 0 ? win0[ub] : (xz == 1 ? win1[ub] : 0.f));
-                            const float c = tanhf_(rr * m + cin);
-                            const float hp = hreg[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)][ii];
+                            const int ud = ub % (DIMS == 1 ? UB : 1);
+                            const float uu = sigmoidf_(g0);
+                            const float rr = sigmoidf_(g1);
+                            const float cin = bin_[ud][i] + (xz == 0 ? win0[ud][i] : (xz == 1 ? win1[ud][i] : 0.f));
+                            const float c = tanhf_(rr * g2 + cin);
+                            float &hp = hreg[rb % (DIMS == 1 ? RB : 1)][ud][i];
                             h = (1.0f - uu) * hp + uu * c;
-                            hreg[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)][ii] = h;
-                            s0 = uu; s1 = rr; s2 = m; s3 = c;
+                            hp = h;
+                            s0 = uu; s1 = rr; s2 = g2; s3 = c;
                         } else {
-                            const float c = tanhf_(g0 + bias0[ub]);
-                            const float uu = sigmoidf_(g1 + bias1[ub]);
+                            const float c = tanhf_(g0);
+                            const float uu = sigmoidf_(g1);
                             h = uu * c + (1.0f - uu) * g2;
                             s0 = c; s1 = uu; s2 = g2;
                         }
-                        hv[rb][ub][ii] = (STORE && s < 0) ? 0.f : h;
-                        if (DIMS == 2) sH[cb][r * H_LD + u] = cvt<P>(h);
-                        if (s >= 0 && store_h) a.hcache[((int64_t)q * ns_c + s) * DH + u] = h;
+                        hq[i] = (STORE && s < 0) ? 0.f : h;
                         if (STORE) {
                             const bool ok = s >= 0;
-                            gvs[0][ub % UB][ii] = ok ? s0 : 0.f;
-                            gvs[STORE ? 1 : 0][ub % UB][ii] = ok ? s1 : 0.f;
-                            gvs[STORE ? 2 : 0][ub % UB][ii] = ok ? s2 : 0.f;
-                            gvs[STORE ? 3 : 0][ub % UB][ii] = ok ? s3 : 0.f;
+                            gv[0][i] = ok ? s0 : 0.f;
+                            gv[STORE ? 1 : 0][i] = ok ? s1 : 0.f;
+                            gv[STORE ? 2 : 0][i] = ok ? s2 : 0.f;
+                            gv[STORE ? 3 : 0][i] = ok ? s3 : 0.f;
+                        }
+                    }
+                    put4<P>(&sH[cb][r * H_LD + u0], hq);
+                    if (!glu) head_part(ub, hq, p0, p1, p2, p3);
+                    if (STORE) {
+                        if (s >= 0 && store_h)
+                            *(float4 *)&a.hcache[((int64_t)q * ns_c + s) * DH + u0] =
+                                make_float4(hq[0], hq[1], hq[2], hq[3]);
+                        const int64_t sx = e0 + r;
+                        if (store_act && sx < a.nsp) {
+#pragma unroll
+                            for (int i = 0; i < 4; i++) {
+                                ((T *)a.hT)[((int64_t)q * DH + u0 + i) * a.nsp + sx] = cvt<P>(hq[i]);
+#pragma unroll
+                                for (int f = 0; f < NA; f++)
+                                    a.act[((int64_t)q * (NA + 2) * DH + f * DH + u0 + i) * a.nsp + sx] =
+                                        gv[STORE ? f : 0][i];
+                            }
                         }
                     }
                 }
-                if (store_act) {
-                    const int64_t s0 = e0 + wr * C::RW + rb * 16 + 4 * lq;
-                    if (s0 < a.nsp) {
-#pragma unroll
-                        for (int ub = 0; ub < UB; ub++) {
-                            const int u = wu * C::UW + ub * 16 + l16;
-                            store4<P>((T *)a.hT + ((int64_t)q * DH + u) * a.nsp + s0, hv[rb][ub][0], hv[rb][ub][1],
-                                      hv[rb][ub][2], hv[rb][ub][3]);
-#pragma unroll
-                            for (int f = 0; f < NA; f++)
-                                *(float4 *)&a.act[((int64_t)q * (NA + 2) * DH + f * DH + u) * a.nsp + s0] =
-                                    make_float4(gvs[STORE ? f : 0][ub][0], gvs[STORE ? f : 0][ub][1],
-                                                gvs[STORE ? f : 0][ub][2], gvs[STORE ? f : 0][ub][3]);
-                        }
-                    }
-                }
+                if (!glu) head_out(r, p0, p1, p2, p3);
             };
             if (REGW) {
                 // branch-free variants per input pattern; the MFMAs of row
@@ -468,7 +505,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                             for (int g = 0; g < 3; g++)
 #pragma unroll
                                 for (int ub = 0; ub < UB; ub++)
-                                    P::mma(acc[g * UB + ub], af, wreg[REGW ? g : 0][REGW ? ks : 0][REGW ? ub : 0]);
+                                    P::mma(acc[g * UB + ub], wreg[REGW ? g : 0][REGW ? ks : 0][REGW ? ub : 0], af);
                         }
                     };
                     f32x4_t acc[2][3 * UB];
@@ -509,23 +546,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                             const int n = g * DH + wu * C::UW + ub * 16 + l16;
                             const uint4 bf = *(const uint4 *)&Bc[(int64_t)n * KPX + ks * KS + VEC * lq];
 #pragma unroll
-                            for (int rb = 0; rb < RB; rb++) P::mma(acc[rb][g * UB + ub], af[rb], bf);
+                            for (int rb = 0; rb < RB; rb++) P::mma(acc[rb][g * UB + ub], bf, af[rb]);
                         }
                 }
 #pragma unroll
                 for (int rb = 0; rb < RB; rb++) epilogue(rb, acc[rb]);
-            }
-            if (DIMS == 1) {
-                // in 1D the operand buffer of this step is sH[pb]; writing
-                // sH[cb] could not race, but keep one writer pattern for both
-#pragma unroll
-                for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-                    for (int ii = 0; ii < 4; ii++)
-#pragma unroll
-                        for (int ub = 0; ub < UB; ub++)
-                            sH[cb][(wr * C::RW + rb * 16 + 4 * lq + ii) * H_LD + wu * C::UW + ub * 16 + l16] =
-                                cvt<P>(hv[rb][ub][ii]);
             }
             __syncthreads();
 
@@ -541,88 +566,50 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 
             // 4. GLU (MFMA) and heads (FP32)
             auto glu_epilogue = [&](int rb, const f32x4_t *acc2) {
-                float part[4][4], gk[UB][4], ga1[STORE ? UB : 1][4], ga2[STORE ? UB : 1][4];
+                const int r = wr * C::RW + rb * 16 + l16;
+                const int s = sRow[r];
+                float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
 #pragma unroll
-                for (int ii = 0; ii < 4; ii++)
+                for (int ub = 0; ub < UB; ub++) {
+                    float g[4], a1[4], a2[4];
 #pragma unroll
-                    for (int o = 0; o < 4; o++) part[ii][o] = 0.f;
-#pragma unroll
-                for (int ii = 0; ii < 4; ii++) {
-                    const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
-                    const int s = sRow[r];
-#pragma unroll
-                    for (int ub = 0; ub < UB; ub++) {
-                        const int u = wu * C::UW + ub * 16 + l16;
-                        float g;
-                        if (glu) {
-                            const float a1 = acc2[ub][ii] + gb1[ub];
-                            const float a2 = acc2[UB + ub][ii] + gb2[ub];
-                            g = a1 * sigmoidf_(a2);
-                            if (STORE) {
-                                ga1[ub % UB][ii] = s >= 0 ? a1 : 0.f;
-                                ga2[ub % UB][ii] = s >= 0 ? a2 : 0.f;
-                            }
-                        } else {
-                            g = hv[rb][ub][ii];
-                        }
-                        part[ii][0] += hw[0][ub] * g;
-                        part[ii][1] += hw[1][ub] * g;
-                        if (cplx) {
-                            part[ii][2] += hw[2][ub] * g;
-                            part[ii][3] += hw[3][ub] * g;
-                        }
-                        if (STORE) gk[ub][ii] = s >= 0 ? g : 0.f;
+                    for (int i = 0; i < 4; i++) {
+                        a1[i] = acc2[ub][i] + gb1[ub][i];
+                        a2[i] = acc2[UB + ub][i] + gb2[ub][i];
+                        g[i] = a1[i] * sigmoidf_(a2[i]);
                     }
-                }
-                if (store_act && glu) {
-                    const int64_t s0 = e0 + wr * C::RW + rb * 16 + 4 * lq;
-                    if (s0 < a.nsp) {
+                    head_part(ub, g, p0, p1, p2, p3);
+                    const int64_t sx = e0 + r;
+                    if (store_act && sx < a.nsp) {
+                        const bool ok = s >= 0;
+                        const int u0 = unit0(ub);
 #pragma unroll
-                        for (int ub = 0; ub < UB; ub++) {
-                            const int u = wu * C::UW + ub * 16 + l16;
-                            store4<P>((T *)a.gT + ((int64_t)q * DH + u) * a.nsp + s0, gk[ub][0], gk[ub][1], gk[ub][2],
-                                      gk[ub][3]);
-                            float *fa = &a.act[((int64_t)q * (NA + 2) * DH + NA * DH + u) * a.nsp + s0];
-                            *(float4 *)fa = make_float4(ga1[ub % UB][0], ga1[ub % UB][1], ga1[ub % UB][2], ga1[ub % UB][3]);
-                            *(float4 *)(fa + (int64_t)DH * a.nsp) =
-                                make_float4(ga2[ub % UB][0], ga2[ub % UB][1], ga2[ub % UB][2], ga2[ub % UB][3]);
+                        for (int i = 0; i < 4; i++) {
+                            ((T *)a.gT)[((int64_t)q * DH + u0 + i) * a.nsp + sx] = cvt<P>(ok ? g[i] : 0.f);
+                            float *fa = &a.act[((int64_t)q * (NA + 2) * DH + NA * DH + u0 + i) * a.nsp + sx];
+                            fa[0] = ok ? a1[i] : 0.f;
+                            fa[(int64_t)DH * a.nsp] = ok ? a2[i] : 0.f;
                         }
                     }
                 }
-#pragma unroll
-                for (int ii = 0; ii < 4; ii++) {
-                    const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
-                    const float v0 = row16_sum(part[ii][0]);
-                    const float v1 = row16_sum(part[ii][1]);
-                    float v2 = 0.f, v3 = 0.f;
-                    if (cplx) {
-                        v2 = row16_sum(part[ii][2]);
-                        v3 = row16_sum(part[ii][3]);
-                    }
-                    if (l16 == 0) *(float4 *)&sLog[wu][r][0] = make_float4(v0, v1, v2, v3);
-                }
+                head_out(r, p0, p1, p2, p3);
             };
             auto glu_frag = [&](int rb, int kk) -> uint4 {
                 const int arow = wr * C::RW + rb * 16 + l16;
                 return *(const uint4 *)&sH[cb][arow * H_LD + kk + VEC * lq];
             };
-            if (!glu) {
-#pragma unroll
-                for (int rb = 0; rb < RB; rb++) glu_epilogue(rb, nullptr);
-            } else if (REGW) {
+            if (glu && REGW) {
                 auto gblock = [&](int rb, f32x4_t *acc2) {
 #pragma unroll
                     for (int c = 0; c < 2 * UB; c++) acc2[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int kk = 0; kk < KHB; kk += KS) {
-                        const uint4 af = glu_frag(rb, kk);
+                    for (int kq = 0; kq < NKG; kq++) {
+                        const uint4 af = glu_frag(rb, kq * KS);
 #pragma unroll
                         for (int g = 0; g < 2; g++)
 #pragma unroll
-                            for (int ub = 0; ub < UB; ub++) {
-                                const int n = g * DH + wu * C::UW + ub * 16 + l16;
-                                P::mma(acc2[g * UB + ub], af, *(const uint4 *)&sG[n * GLD + kk + VEC * lq]);
-                            }
+                            for (int ub = 0; ub < UB; ub++)
+                                P::mma(acc2[g * UB + ub], wgl[REGW ? g : 0][REGW ? kq : 0][REGW ? ub : 0], af);
                     }
                 };
                 f32x4_t acc2[2][2 * UB];
@@ -632,7 +619,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                     if (rb + 1 < RB) gblock(rb + 1, acc2[(rb + 1) & 1]);
                     glu_epilogue(rb, acc2[rb & 1]);
                 }
-            } else {
+            } else if (glu) {
                 f32x4_t acc2[RB][2 * UB];
 #pragma unroll
                 for (int rb = 0; rb < RB; rb++)
@@ -650,7 +637,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                             const int n = g * DH + wu * C::UW + ub * 16 + l16;
                             const uint4 bf = *(const uint4 *)&Bg[(int64_t)n * KHB + kk + VEC * lq];
 #pragma unroll
-                            for (int rb = 0; rb < RB; rb++) P::mma(acc2[rb][g * UB + ub], af[rb], bf);
+                            for (int rb = 0; rb < RB; rb++) P::mma(acc2[rb][g * UB + ub], bf, af[rb]);
                         }
                 }
 #pragma unroll

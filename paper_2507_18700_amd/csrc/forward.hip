@@ -10,8 +10,9 @@ namespace vmc {
 //  Bc  [3*DH][KPX]: per gate row n = gate*DH + unit, the hidden block(s) of
 //      width KHB (1D: h; 2D: h_hz then h_vt, zero-padded) followed by one
 //      indicator block of width KS holding the one-hot columns of the gate
-//      matrices (FP32: one column per class; BF16: a hi and a lo bfloat16
-//      column per class, hi + lo = the FP32 weight to ~2^-16).
+//      matrices (classes 0..3) and the gate biases (class 4), FP32: one
+//      column per class; BF16: a hi and a lo bfloat16 column per class,
+//      hi + lo = the FP32 weight to ~2^-16.
 //  BcT [NHB*DH][NCP]: the hidden part transposed (backward), NCP >= 3*DH.
 //  Bg  [2*DH][KHB], BgT [KHB][2*DH]: GLU (W_1 rows, then W_2 rows).
 template <class P>
@@ -43,6 +44,11 @@ __global__ void stage_weights(Dims d, const float *__restrict__ prm, typename P:
         if (d.dims == 1) return prm[(g == 0 ? L.Wg : L.Wr) + (int64_t)u * (dh + 2) + dh + c];
         return prm[(g == 0 ? L.W : L.Wg) + (int64_t)u * (2 * dh + 4) + 2 * dh + c];
     };
+    // bias of gate g, unit u (2D: the U h' gate has none)
+    auto gate_bias = [&](int g, int u) -> float {
+        if (d.dims == 1) return prm[(g == 0 ? L.bg : g == 1 ? L.br : L.bh) + u];
+        return g == 0 ? prm[L.b + u] : g == 1 ? prm[L.bg + u] : 0.0f;
+    };
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = e;
@@ -54,17 +60,19 @@ __global__ void stage_weights(Dims d, const float *__restrict__ prm, typename P:
                 if (k < NHB * KHB) {
                     const int blk = k / KHB, kk = k % KHB;
                     if (kk < dh) v = hid(g, u, blk * dh + kk);
-                } else if (g < 2) {
+                } else {
+                    // indicator block: one-hot classes 0..nx-1, then the gate
+                    // bias as class 4 (its indicator is always on)
                     const int xc = k - NHB * KHB;
+                    const int c = KS == 32 ? xc >> 1 : xc;
+                    float w = 0.0f;
+                    if (c < nx && g < 2) w = onehot(g, u, c);
+                    else if (c == 4) w = gate_bias(g, u);
                     if (KS == 32) {  // bfloat16: hi, lo per class
-                        const int c = xc >> 1;
-                        if (c < nx) {
-                            const float w = onehot(g, u, c);
-                            const float hi = bf2f(f2bf(w));
-                            v = (xc & 1) ? w - hi : hi;
-                        }
-                    } else if (xc < nx) {
-                        v = onehot(g, u, xc);
+                        const float hi = bf2f(f2bf(w));
+                        v = (xc & 1) ? w - hi : hi;
+                    } else {
+                        v = w;
                     }
                 }
             }

@@ -67,10 +67,7 @@ __device__ inline void store4<F32>(float *dst, float a0, float a1, float a2, flo
 }
 template <>
 __device__ inline void store4<BF16>(uint16_t *dst, float a0, float a1, float a2, float a3) {
-    uint2 v;
-    v.x = (uint32_t)f2bf(a0) | ((uint32_t)f2bf(a1) << 16);
-    v.y = (uint32_t)f2bf(a2) | ((uint32_t)f2bf(a3) << 16);
-    *(uint2 *)dst = v;
+    *(uint2 *)dst = make_uint2(pack_bf16x2(a0, a1), pack_bf16x2(a2, a3));
 }
 
 __host__ __device__ constexpr int cround(int x, int m) { return (x + m - 1) / m * m; }
