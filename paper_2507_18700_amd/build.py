@@ -13,7 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvmcrnn.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "engine.hip", "backward.hip", "forward.hip", "grad.hip", "grow.hip"]
+SOURCES = ["api.hip", "engine.hip", "engine_bf16_1d.hip", "engine_bf16_2d.hip", "engine_f32_1d.hip",
+           "engine_f32_2d.hip", "backward.hip", "forward.hip", "grad.hip", "grow.hip"]
 ARCH = "gfx950"
 
 

@@ -7,7 +7,7 @@
 namespace vmc {
 
 hipError_t launch_stage(const Dims &d, const float *prm, void *Bc, void *BcT, void *Bg, void *BgT,
-                        float *E, float *Hd, float *hc, hipStream_t st);
+                        float *E, float *Hd, float *hc, int4 *postab, hipStream_t st);
 hipError_t launch_forward(const FwdArgs &a, int mode, int store_h, int store_lpc, int store_act,
                           int grid, hipStream_t st);
 hipError_t launch_sched(int ham_kind, int Lx, int Ly, int64_t ns, const uint8_t *cfg, int *cnt,
@@ -17,7 +17,8 @@ hipError_t launch_assemble(const vmc_ham &H, int Lx, int Ly, int64_t ns, const u
                            const float *lpc, const float *phc, const double2 *pre, const double2 *dsuf, int NC,
                            double *eloc, hipStream_t st);
 int engine_kpx(const Dims &d);
-int forward_tile_rows(int DH);
+size_t engine_lds(const Dims &d);
+int forward_tile_rows(const Dims &d);
 int backward_tile_rows(int DH);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
 hipError_t launch_grad(const GradBufs &b, hipStream_t st);
@@ -28,6 +29,7 @@ hipError_t launch_grow(const vmc_model &from, const float *p0, int new_dh, uint6
                        int64_t n_to, hipStream_t st);
 
 static const int kMaxN = 1024;
+static const size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 
 static bool valid_model(const vmc_model *m) {
     if (!m) return false;
@@ -82,7 +84,7 @@ static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 // Workspace map; offsets in bytes from the workspace base.
 struct WsMap {
     size_t Bc, BcT, Bg, BgT, E, Hd, hc;
-    size_t hcache, lpc, phc, pre, dsuf;
+    size_t hcache, hcs, postab, lpc, phc, pre, dsuf;
     size_t cnt, list_off, tile_start, tile_counter, list;
     size_t colbuf;
     size_t act, lgT, hT, gT, xT, dtc, dtg, dth, dcol, part, stats;
@@ -96,7 +98,7 @@ static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
     memset(&w, 0, sizeof(w));
     const size_t es = d.prec == VMC_BF16 ? 2 : 4;
     const int KGP = round_up(d.DH, d.prec == VMC_BF16 ? 32 : 16);
-    const int MT = forward_tile_rows(d.DH);
+    const int MT = forward_tile_rows(d);
     size_t o = 0;
     auto put = [&](size_t bytes) {
         size_t at = o;
@@ -111,6 +113,8 @@ static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
     w.Hd = put((size_t)4 * d.DH * 4);
     w.hc = put(16);
     w.hcache = put((size_t)d.N * ns * d.DH * 4);
+    w.hcs = d.prec == VMC_BF16 ? put((size_t)d.N * ns * d.DH * 2) : w.hcache;
+    w.postab = put((size_t)d.N * 16);
     w.lpc = put((size_t)ns * d.N * 2 * 4);
     w.phc = put((size_t)ns * d.N * 2 * 4);
     w.pre = put((size_t)ns * d.N * 16);
@@ -161,7 +165,8 @@ static vmc_status check_common(const vmc_model *m, const float *params, int64_t 
     if (padded_dh(m->d_h) < 0) return VMC_EUNSUPPORTED;
     if (n >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
     Dims d = make_dims(m);
-    if ((int64_t)forward_tile_rows(d.DH) * d.N > 32768) return VMC_EUNSUPPORTED;
+    if ((int64_t)forward_tile_rows(d) * d.N > 32768) return VMC_EUNSUPPORTED;
+    if (engine_lds(d) > kMaxLds) return VMC_EUNSUPPORTED;
     if (H && H->kind == VMC_HEISENBERG && n * bond_count(d.Lx, d.Ly) >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
     WsMap w = ws_map(d, H, n);
     if (need) *need = w.total;
@@ -171,7 +176,8 @@ static vmc_status check_common(const vmc_model *m, const float *params, int64_t 
 
 static hipError_t stage(const Dims &d, const float *params, void *ws, const WsMap &w, hipStream_t st) {
     return launch_stage(d, params, at<void>(ws, w.Bc), at<void>(ws, w.BcT), at<void>(ws, w.Bg),
-                        at<void>(ws, w.BgT), at<float>(ws, w.E), at<float>(ws, w.Hd), at<float>(ws, w.hc), st);
+                        at<void>(ws, w.BgT), at<float>(ws, w.E), at<float>(ws, w.Hd), at<float>(ws, w.hc),
+                        at<int4>(ws, w.postab), st);
 }
 
 static FwdArgs base_args(const Dims &d, void *ws, const WsMap &w, int64_t ns) {
@@ -186,6 +192,8 @@ static FwdArgs base_args(const Dims &d, void *ws, const WsMap &w, int64_t ns) {
     a.nrows = ns;
     a.ns_cache = ns;
     a.colbuf = at<void>(ws, w.colbuf);
+    a.postab = at<int4>(ws, w.postab);
+    a.hcs = at<void>(ws, w.hcs);
     return a;
 }
 
@@ -267,7 +275,7 @@ vmc_status rnn_logpsi(const vmc_model *m, const float *params, int64_t nc, const
 // conditionals, prefix sums) holds the configurations.
 static vmc_status eloc_from_cache(const Dims &d, const WsMap &w, void *ws, const vmc_ham *H, int64_t ns,
                                   const uint8_t *configs, double *eloc, hipStream_t st) {
-    const int MT = forward_tile_rows(d.DH);
+    const int MT = forward_tile_rows(d);
     FwdArgs a = base_args(d, ws, w, ns);
     a.cfg_in = configs;
     a.hcache = at<float>(ws, w.hcache);
@@ -338,7 +346,7 @@ vmc_status local_energy(const vmc_model *m, const float *params, const vmc_ham *
     hipStream_t st = (hipStream_t)stream;
     Dims d = make_dims(m);
     WsMap w = ws_map(d, H, ns);
-    const int MT = forward_tile_rows(d.DH);
+    const int MT = forward_tile_rows(d);
     hipError_t e = stage(d, params, ws, w, st);
     if (e != hipSuccess) return VMC_EDEVICE;
     // 1. teacher-forced pass: prefix hidden states and conditionals of every sample

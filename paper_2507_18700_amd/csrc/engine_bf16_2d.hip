@@ -1,0 +1,10 @@
+// Forward-engine instantiations: BF16, 2D chains.
+#include "engine_impl.h"
+
+namespace vmc {
+
+hipError_t launch_engine_bf16_2d(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
+    return launch_engine_d<BF16, 2>(a, mode, sh, sl, sa, grid, st);
+}
+
+}  // namespace vmc

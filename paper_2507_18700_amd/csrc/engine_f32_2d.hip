@@ -1,0 +1,10 @@
+// Forward-engine instantiations: F32, 2D chains.
+#include "engine_impl.h"
+
+namespace vmc {
+
+hipError_t launch_engine_f32_2d(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
+    return launch_engine_d<F32, 2>(a, mode, sh, sl, sa, grid, st);
+}
+
+}  // namespace vmc

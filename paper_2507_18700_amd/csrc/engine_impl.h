@@ -1,0 +1,808 @@
+// Forward engine of the GRU RNN wave function on gfx950 (kernel template;
+// instantiated per precision and dimension in engine_*.hip).
+//
+// One kernel runs the autoregressive chain (Eq. 1) for a tile of rows over a
+// range of order positions.  A row is a sample (sampling, Sec. II A, or the
+// teacher-forced log psi) or a connected configuration of the local energy
+// (the chain after its first changed order position, Eqs. 6-7).  Per order
+// position q a tile does:
+//   1. operands in LDS: the hidden input(s) (1D: h_{n-1}; 2D: [h_hz | h_vt],
+//      App. A) and an indicator block that carries the one-hot inputs and a
+//      constant column, so the one-hot columns and the biases of the gate
+//      matrices ride on the MFMA (bfloat16: hi/lo split of those weights,
+//      i.e. ~16 significant bits);
+//   2. the cell contraction on MFMA, each wave owning all gate columns of a
+//      slice of hidden units, so the App. A gate algebra runs in registers on
+//      the MFMA output;
+//   3. the optional GLU contraction on MFMA;
+//   4. the 2- or 4-logit heads (Eqs. 3, 5) in FP32 as lane partial dot
+//      products, a sum over the lane groups and a cross-wave sum in LDS;
+//   5. a per-row finalisation: log-softmax, the sampling decision or the
+//      teacher-forced spin, FP64 accumulation of log P and the phase.
+// The weights are the MFMA A operand, so a lane owns 4 consecutive hidden
+// units of one row: the new h goes to LDS as one 8- or 16-byte store and a
+// head sum needs only the four lane groups of a row.  With REGW the cell and
+// GLU weights stay in registers for the whole persistent launch; otherwise
+// both stream from L2.
+//
+// Teacher-forced rows (log psi, local energy) know every input in advance,
+// so one workgroup barrier per position suffices: the phase of position q
+// runs the GLU and heads of q, the cell of q+1, the operand staging of q+2
+// and the finalisation of q-1, on double-buffered hidden, vertical and
+// indicator tiles and triple-buffered head sums.  Sampling draws the spin of
+// q before the cell of q+1 can start and keeps three barriers per position.
+#pragma once
+#include <type_traits>
+
+#include "kernels.h"
+
+namespace vmc {
+
+template <class P, int DIMS, int DH, int NW>
+struct Eng {
+    static constexpr int WU = (DH / 16 < NW) ? DH / 16 : NW;  // waves along hidden units
+    static constexpr int WR = NW / WU;                        // waves along rows
+    static constexpr int UW = DH / WU;
+    static constexpr int UB = UW / 16;
+    // rows per tile (FP32 tiles at d_h >= 128 are halved to fit the LDS)
+    static constexpr int MT = (DH >= 256 || (P::VEC == 4 && DH >= 128)) ? 32 : 64;
+    static constexpr int RW = MT / WR;
+    static constexpr int RB = RW / 16;
+    static constexpr int FR = MT / NW;                         // rows finalised per wave
+    static constexpr int KS = P::KSTEP;
+    static constexpr int KHB = cround(DH, KS);                 // one hidden block of the operand
+    static constexpr int NKB = KHB / KS;                       // k-steps per hidden block
+    static constexpr int NHB = DIMS == 1 ? 1 : 2;              // hidden blocks (hz, vt)
+    static constexpr int NKS = NHB * NKB + 1;                  // + the indicator step
+    static constexpr int KPX = NKS * KS;                       // staged row length of Bc
+    static constexpr int PADE = 16 / (int)sizeof(typename P::store_t);
+    static constexpr int H_LD = KHB + PADE;                    // row stride of sH / sV
+    static constexpr int X_LD = KS + PADE;                     // row stride of the indicator tile
+    static constexpr int NLOG = 3;                             // head-sum buffers
+    // static LDS of the kernel (bytes), for the host-side capacity check
+    static constexpr size_t LDS =
+        sizeof(typename P::store_t) * ((size_t)2 * MT * H_LD + (DIMS == 2 ? 2 * MT * H_LD : 8) + 2 * MT * X_LD) +
+        4 * ((size_t)NLOG * WU * MT * 4 + 2 * DH) + 4 * MT + 16;
+};
+
+// Sum over the four 16-lane groups of a wave (lanes l, l^16, l^32, l^48);
+// every lane gets the sum, with the same bits in all four lanes.  Two
+// cross-row swaps (v_permlane16_swap, v_permlane32_swap) and two adds.
+__device__ inline float group4_sum(float v) {
+    const uint32_t b = __float_as_uint(v);
+    const auto x = __builtin_amdgcn_permlane16_swap(b, b, false, false);
+    const float s = __uint_as_float(x[0]) + __uint_as_float(x[1]);
+    const uint32_t c = __float_as_uint(s);
+    const auto y = __builtin_amdgcn_permlane32_swap(c, c, false, false);
+    return __uint_as_float(y[0]) + __uint_as_float(y[1]);
+}
+
+// Four consecutive units of one row (one 8- or 16-byte store).
+template <class P>
+__device__ inline void put4(typename P::store_t *dst, const float *v);
+template <>
+__device__ inline void put4<F32>(float *dst, const float *v) {
+    *(float4 *)dst = make_float4(v[0], v[1], v[2], v[3]);
+}
+template <>
+__device__ inline void put4<BF16>(uint16_t *dst, const float *v) {
+    *(uint2 *)dst = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+}
+
+template <class P>
+__device__ inline typename P::store_t cvt(float x);
+template <>
+__device__ inline float cvt<F32>(float x) { return x; }
+template <>
+__device__ inline uint16_t cvt<BF16>(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+
+// Facts of one order position (the position table, see build_postab).
+struct PosInfo {
+    int site, site_hz, site_vt, pos_vt, icol;
+    bool colw;  // h of this position is a later vertical input (kept in the column buffer)
+};
+
+template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF>
+__global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int store_h_, int store_lpc_,
+                                                      int store_act_) {
+    // cache writes exist only in the STORE variant (the chain kernel has none)
+    const int store_h = STORE && store_h_, store_lpc = STORE && store_lpc_, store_act = STORE && store_act_;
+    typedef Eng<P, DIMS, DH, NW> C;
+    typedef typename P::store_t T;
+    constexpr int MT = C::MT, RB = C::RB, UB = C::UB, KS = C::KS, VEC = P::VEC, FR = C::FR;
+    constexpr int KHB = C::KHB, NKB = C::NKB, NKS = C::NKS, KPX = C::KPX;
+    constexpr int H_LD = C::H_LD, X_LD = C::X_LD, NT = NW * 64;
+    constexpr int NKG = KHB / KS;          // k-steps of the GLU contraction
+    constexpr int NA = DIMS == 1 ? 4 : 3;  // gate features; the GLU pair follows
+    constexpr int NCH = MT * (DH / VEC), PF = (NCH + NT - 1) / NT;  // 16-byte chunks of an h tile
+
+    __shared__ __align__(16) T sH[2][MT * H_LD];
+    __shared__ __align__(16) T sV[DIMS == 2 ? 2 : 1][DIMS == 2 ? MT * H_LD : 8];
+    __shared__ __align__(16) T sX[2][MT * X_LD];
+    __shared__ __align__(16) float sLog[C::NLOG][C::WU][MT][4];
+    __shared__ __align__(16) float sHw[2][DH];  // phase-head rows (complex amplitudes)
+    __shared__ int sRow[MT];
+    __shared__ int sTile;
+    extern __shared__ uint8_t sSig[];  // [MT][N]
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w / C::WU, wu = w % C::WU;
+    const int N = a.d.N, Lx = a.d.Lx, Ly = a.d.Ly;
+    const int cplx = a.d.cplx, glu = a.d.glu;
+    const T *__restrict__ Bc = (const T *)a.Bc;
+    const T *__restrict__ Bg = (const T *)a.Bg;
+    const T *__restrict__ hcs = (const T *)a.hcs;
+    const int4 *__restrict__ postab = a.postab;
+    const int64_t ns_c = a.ns_cache;
+    T *colbuf = (T *)a.colbuf + (int64_t)blockIdx.x * Lx * MT * DH;
+    const int l16 = lane & 15, lq = lane >> 4;
+    // row finalised by this lane (FR rows per wave)
+    const bool owner = lane < FR;
+    const int orow = w * FR + lane;
+    auto unit0 = [&](int ub) __attribute__((always_inline)) { return wu * C::UW + ub * 16 + 4 * lq; };
+
+    // per-lane constants of this lane's units: GLU biases, amplitude head
+    float gb1[UB][4], gb2[UB][4], hw0[UB][4], hw1[UB][4];
+    float bin_[DIMS == 1 ? UB : 1][4], win0[DIMS == 1 ? UB : 1][4], win1[DIMS == 1 ? UB : 1][4];
+#pragma unroll
+    for (int ub = 0; ub < UB; ub++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int u = unit0(ub) + i;
+            gb1[ub][i] = a.E[E_B1 * DH + u];
+            gb2[ub][i] = a.E[E_B2 * DH + u];
+            hw0[ub][i] = a.Hd[u];
+            hw1[ub][i] = a.Hd[DH + u];
+            if (DIMS == 1) {
+                bin_[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_BIN * DH + u];
+                win0[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_XIN0 * DH + u];
+                win1[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_XIN1 * DH + u];
+            }
+        }
+    for (int e = tid; e < 2 * DH; e += NT) (&sHw[0][0])[e] = a.Hd[2 * DH + e];
+    const float hc0 = a.hc[0], hc1 = a.hc[1], hc2 = a.hc[2], hc3 = a.hc[3];
+
+    // REGW: cell and GLU weight fragments in registers for the whole launch
+    i32x4_t wreg[REGW ? 3 : 1][REGW ? NKS : 1][REGW ? UB : 1];
+    uint4 wgl[REGW ? 2 : 1][REGW ? NKG : 1][REGW ? UB : 1];
+    if (REGW) {
+#pragma unroll
+        for (int g = 0; g < 3; g++)
+#pragma unroll
+            for (int ks = 0; ks < NKS; ks++)
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    const int n = g * DH + wu * C::UW + ub * 16 + l16;
+                    wreg[g][ks][ub] = *(const i32x4_t *)&Bc[(int64_t)n * KPX + ks * KS + VEC * lq];
+                }
+#pragma unroll
+        for (int g = 0; g < 2; g++)
+#pragma unroll
+            for (int kq = 0; kq < NKG; kq++)
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    const int n = g * DH + wu * C::UW + ub * 16 + l16;
+                    wgl[g][kq][ub] = *(const uint4 *)&Bg[(int64_t)n * KHB + kq * KS + VEC * lq];
+                }
+    }
+    // zero the operand tiles once (padding columns stay zero); the bias
+    // class of the indicator block is always on
+    for (int e = tid; e < 2 * MT * H_LD; e += NT) (&sH[0][0])[e] = cvt<P>(0.f);
+    if (DIMS == 2)
+        for (int e = tid; e < 2 * MT * H_LD; e += NT) (&sV[0][0])[e] = cvt<P>(0.f);
+    for (int e = tid; e < 2 * MT * X_LD; e += NT) {
+        const int c = e % X_LD;
+        const bool bias_col = VEC == 8 ? (c == 8 || c == 9) : c == 4;
+        (&sX[0][0])[e] = cvt<P>(bias_col ? 1.f : 0.f);
+    }
+
+    auto pos = [&](int qn) -> PosInfo __attribute__((always_inline)) {
+        const int4 t = postab[qn];
+        PosInfo r;
+        r.site = t.x & 0xFFFF;
+        r.colw = DIMS == 2 && ((t.x >> 16) & 1);
+        r.site_hz = t.y;
+        r.site_vt = DIMS == 2 ? t.z : -1;
+        r.pos_vt = (t.w & 0xFFFF) - 1;
+        r.icol = t.w >> 16;
+        return r;
+    };
+
+    // Head outputs of one 16-row block: sum the lane partials over the four
+    // lane groups of a row, then one lane group stores the wave's sums.
+    auto head_out = [&](int lb, int r, float p0, float p1, float p2, float p3) __attribute__((always_inline)) {
+        p0 = group4_sum(p0);
+        p1 = group4_sum(p1);
+        if (cplx) {
+            p2 = group4_sum(p2);
+            p3 = group4_sum(p3);
+        }
+        if (lq == 0) *(float4 *)&sLog[lb][wu][r][0] = make_float4(p0, p1, p2, p3);
+    };
+    // partial head sums of the lane's 4 units of one row
+    auto head_part = [&](int ub, const float *g, float &p0, float &p1, float &p2, float &p3) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            p0 += hw0[ub][i] * g[i];
+            p1 += hw1[ub][i] * g[i];
+        }
+        if (cplx) {
+            const float4 z0 = *(const float4 *)&sHw[0][unit0(ub)];
+            const float4 z1 = *(const float4 *)&sHw[1][unit0(ub)];
+            p2 += z0.x * g[0] + z0.y * g[1] + z0.z * g[2] + z0.w * g[3];
+            p3 += z1.x * g[0] + z1.y * g[1] + z1.z * g[2] + z1.w * g[3];
+        }
+    };
+
+    bool first = true;
+    for (;;) {
+        // ---------------------------------------------------------- tile
+        int p = -1, nrow;
+        int64_t e0;
+        if (mode == MODE_CHAIN) {
+            __syncthreads();
+            if (tid == 0) sTile = atomicAdd(a.tile_counter, 1);
+            __syncthreads();
+            const int t = sTile;
+            if (t >= a.tile_start[N]) break;
+            int lo = 0, hi = N - 1;  // largest p with tile_start[p] <= t
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (a.tile_start[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            p = lo;
+            e0 = (int64_t)(t - a.tile_start[p]) * MT;
+            nrow = (int)min((int64_t)MT, (int64_t)a.cnt[p] - e0);
+        } else {
+            if (!first) break;
+            e0 = (int64_t)blockIdx.x * MT;
+            nrow = (int)min((int64_t)MT, a.nrows - e0);
+        }
+        first = false;
+
+        // ------------------------------------------------------ row setup
+        int my_s = -1, f1 = -1, f2 = -1, cidx = 0;  // of row orow (owner lanes)
+        if (owner) {
+            if (orow < nrow) {
+                const int64_t ent = e0 + orow;
+                if (mode != MODE_CHAIN) {
+                    my_s = (int)ent;
+                } else if (a.ham_kind == 0) {
+                    my_s = (int)ent;
+                    f1 = order_site(p, Lx);
+                    cidx = p;
+                } else {
+                    const int conn = a.list[a.list_off[p] + ent];
+                    my_s = conn / a.nbond;
+                    cidx = conn - my_s * a.nbond;
+                    bond_sites(cidx, Lx, Ly, f1, f2);
+                }
+            }
+            sRow[orow] = my_s;
+        }
+        __syncthreads();
+        for (int e = tid; e < MT * N; e += NT) {
+            const int r = e / N, c = e - r * N;
+            const int s = sRow[r];
+            sSig[e] = (s >= 0 && mode != MODE_SAMPLE) ? a.cfg_in[(int64_t)s * N + c] : (uint8_t)0;
+        }
+        __syncthreads();
+        if (owner && my_s >= 0 && mode == MODE_CHAIN) {
+            sSig[orow * N + f1] ^= 1;
+            if (f2 >= 0) sSig[orow * N + f2] ^= 1;
+        }
+        // previous hidden state of the first step: h(p) from the prefix cache
+        float hreg[DIMS == 1 ? RB : 1][DIMS == 1 ? UB : 1][4];
+#pragma unroll
+        for (int rb = 0; rb < (DIMS == 1 ? RB : 1); rb++)
+#pragma unroll
+            for (int ub = 0; ub < (DIMS == 1 ? UB : 1); ub++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) hreg[rb][ub][i] = 0.f;
+        if (p >= 0) {
+            for (int e = tid; e < NCH; e += NT) {
+                const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
+                const int s = sRow[r];
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (s >= 0) v = *(const uint4 *)&hcs[((int64_t)p * ns_c + s) * DH + c];
+                *(uint4 *)&sH[p & 1][r * H_LD + c] = v;
+            }
+            if (DIMS == 1) {
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++) {
+                    const int s = sRow[wr * C::RW + rb * 16 + l16];
+#pragma unroll
+                    for (int ub = 0; ub < UB; ub++) {
+                        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (s >= 0) v = *(const float4 *)&a.hcache[((int64_t)p * ns_c + s) * DH + unit0(ub)];
+                        float *hr = hreg[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)];
+                        hr[0] = v.x;
+                        hr[1] = v.y;
+                        hr[2] = v.z;
+                        hr[3] = v.w;
+                    }
+                }
+            }
+        }
+        double acc_lp = 0.0, acc_ph = 0.0;
+
+        // -------------------------------------------------- phase pieces
+        // vertical input rows of a position (2D, not the row start): from the
+        // prefix cache (positions <= p) or from the column buffer
+        uint4 pfv[PF];
+        auto vt_needed = [&](int qn, const PosInfo &pi) __attribute__((always_inline)) {
+            return DIMS == 2 && pi.site_vt >= 0 && pi.pos_vt < qn - 1;
+        };
+        auto vt_issue = [&](const PosInfo &pi) __attribute__((always_inline)) {
+            const bool cache = pi.pos_vt <= p;
+#pragma unroll
+            for (int i = 0; i < PF; i++) {
+                const int e = tid + i * NT;
+                if (e < NCH) {
+                    const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
+                    if (cache) {
+                        const int s = sRow[r];
+                        pfv[i] = s >= 0 ? *(const uint4 *)&hcs[((int64_t)pi.pos_vt * ns_c + s) * DH + c]
+                                        : make_uint4(0, 0, 0, 0);
+                    } else {
+                        pfv[i] = *(const uint4 *)&colbuf[((int64_t)pi.icol * MT + r) * DH + c];
+                    }
+                }
+            }
+        };
+        auto vt_store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < PF; i++) {
+                const int e = tid + i * NT;
+                if (e < NCH) {
+                    const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
+                    *(uint4 *)&sV[DIMS == 2 ? buf : 0][r * H_LD + c] = pfv[i];
+                }
+            }
+        };
+        // h of position qn into the column buffer (its column's next vertical input)
+        auto col_copy = [&](int qn, const PosInfo &pi) __attribute__((always_inline)) {
+            for (int e = tid; e < NCH; e += NT) {
+                const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
+                *(uint4 *)&colbuf[((int64_t)pi.icol * MT + r) * DH + c] = *(const uint4 *)&sH[qn & 1][r * H_LD + c];
+            }
+        };
+        // indicator columns of position qn for the owned row (one 16-byte store):
+        // FP32 [x_hz0, x_hz1, x_vt0, x_vt1]; BF16 each twice (hi, lo)
+        auto indicator = [&](const PosInfo &pi, int buf) __attribute__((always_inline)) {
+            if (!owner) return;
+            const int xz = pi.site_hz >= 0 ? sSig[orow * N + pi.site_hz] : -1;
+            const int xv = pi.site_vt >= 0 ? sSig[orow * N + pi.site_vt] : -1;
+            const uint32_t one = VEC == 8 ? 0x3F803F80u : 0x3F800000u;
+            *(uint4 *)&sX[buf][orow * X_LD] = make_uint4(xz == 0 ? one : 0u, xz == 1 ? one : 0u,
+                                                         xv == 0 ? one : 0u, xv == 1 ? one : 0u);
+        };
+
+        // cell of position qc: A fragment of row block rb, k-step ks
+        auto a_frag = [&](int qc, bool vt_prev, int rb, int ks) -> uint4 __attribute__((always_inline)) {
+            const int blk = ks / NKB;
+            const bool is_x = ks == NKS - 1;
+            const T *Aop = is_x ? sX[qc & 1] : (blk == 0 || vt_prev) ? sH[(qc - 1) & 1] : sV[DIMS == 2 ? (qc & 1) : 0];
+            const int ald = is_x ? X_LD : H_LD;
+            const int kc = is_x ? 0 : (ks % NKB) * KS;
+            const int arow = wr * C::RW + rb * 16 + l16;
+            return *(const uint4 *)&Aop[arow * ald + kc + VEC * lq];
+        };
+        // gate algebra (App. A) on the cell MFMA output of row block rb
+        auto cell_epi = [&](int qc, const PosInfo &pi, int rb, const f32x4_t *acc) __attribute__((always_inline)) {
+            const int r = wr * C::RW + rb * 16 + l16;
+            const int s = sRow[r];
+            int xz = 0;
+            if (DIMS == 1) xz = pi.site_hz >= 0 ? sSig[r * N + pi.site_hz] : -1;
+            float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll
+            for (int ub = 0; ub < UB; ub++) {
+                const int u0 = unit0(ub);
+                float hq[4], gv[STORE ? 4 : 1][4];
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const float g0 = acc[ub][i], g1 = acc[UB + ub][i], g2 = acc[2 * UB + ub][i];
+                    float h, s0, s1, s2, s3 = 0.f;
+                    if (DIMS == 1) {
+                        const int ud = ub % (DIMS == 1 ? UB : 1);
+                        const float uu = sigmoidf_(g0);
+                        const float rr = sigmoidf_(g1);
+                        const float cin = bin_[ud][i] + (xz == 0 ? win0[ud][i] : (xz == 1 ? win1[ud][i] : 0.f));
+                        const float c = tanhf_(rr * g2 + cin);
+                        float &hp = hreg[rb % (DIMS == 1 ? RB : 1)][ud][i];
+                        h = (1.0f - uu) * hp + uu * c;
+                        hp = h;
+                        s0 = uu; s1 = rr; s2 = g2; s3 = c;
+                    } else {
+                        const float c = tanhf_(g0);
+                        const float uu = sigmoidf_(g1);
+                        h = uu * c + (1.0f - uu) * g2;
+                        s0 = c; s1 = uu; s2 = g2;
+                    }
+                    hq[i] = (STORE && s < 0) ? 0.f : h;
+                    if (STORE) {
+                        const bool ok = s >= 0;
+                        gv[0][i] = ok ? s0 : 0.f;
+                        gv[STORE ? 1 : 0][i] = ok ? s1 : 0.f;
+                        gv[STORE ? 2 : 0][i] = ok ? s2 : 0.f;
+                        gv[STORE ? 3 : 0][i] = ok ? s3 : 0.f;
+                    }
+                }
+                put4<P>(&sH[qc & 1][r * H_LD + u0], hq);
+                if (!glu) head_part(ub, hq, p0, p1, p2, p3);
+                if (STORE) {
+                    if (s >= 0 && store_h) {
+                        *(float4 *)&a.hcache[((int64_t)qc * ns_c + s) * DH + u0] =
+                            make_float4(hq[0], hq[1], hq[2], hq[3]);
+                        if (VEC == 8) put4<P>((T *)a.hcs + ((int64_t)qc * ns_c + s) * DH + u0, hq);
+                    }
+                    const int64_t sx = e0 + r;
+                    if (store_act && sx < a.nsp) {
+#pragma unroll
+                        for (int i = 0; i < 4; i++) {
+                            ((T *)a.hT)[((int64_t)qc * DH + u0 + i) * a.nsp + sx] = cvt<P>(hq[i]);
+#pragma unroll
+                            for (int f = 0; f < NA; f++)
+                                a.act[((int64_t)qc * (NA + 2) * DH + f * DH + u0 + i) * a.nsp + sx] =
+                                    gv[STORE ? f : 0][i];
+                        }
+                    }
+                }
+            }
+            if (!glu) head_out(qc % C::NLOG, r, p0, p1, p2, p3);
+        };
+        // GLU of position qg on its MFMA output of row block rb, and the heads
+        auto glu_epi = [&](int qg, int rb, const f32x4_t *acc2) __attribute__((always_inline)) {
+            const int r = wr * C::RW + rb * 16 + l16;
+            const int s = sRow[r];
+            float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll
+            for (int ub = 0; ub < UB; ub++) {
+                float g[4], a1[4], a2[4];
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    a1[i] = acc2[ub][i] + gb1[ub][i];
+                    a2[i] = acc2[UB + ub][i] + gb2[ub][i];
+                    g[i] = a1[i] * sigmoidf_(a2[i]);
+                }
+                head_part(ub, g, p0, p1, p2, p3);
+                const int64_t sx = e0 + r;
+                if (store_act && sx < a.nsp) {
+                    const bool ok = s >= 0;
+                    const int u0 = unit0(ub);
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        ((T *)a.gT)[((int64_t)qg * DH + u0 + i) * a.nsp + sx] = cvt<P>(ok ? g[i] : 0.f);
+                        float *fa = &a.act[((int64_t)qg * (NA + 2) * DH + NA * DH + u0 + i) * a.nsp + sx];
+                        fa[0] = ok ? a1[i] : 0.f;
+                        fa[(int64_t)DH * a.nsp] = ok ? a2[i] : 0.f;
+                    }
+                }
+            }
+            head_out(qg % C::NLOG, r, p0, p1, p2, p3);
+        };
+        auto glu_frag = [&](int qg, int rb, int kk) -> uint4 __attribute__((always_inline)) {
+            const int arow = wr * C::RW + rb * 16 + l16;
+            return *(const uint4 *)&sH[qg & 1][arow * H_LD + kk + VEC * lq];
+        };
+
+        // One phase: the GLU and heads of position qg (do_glu) and the cell of
+        // position qc (do_cell, input pattern HZ/VT).  With register-resident
+        // weights the MFMAs of the next row block are issued ahead of the
+        // epilogue of the current one, across the GLU -> cell boundary too.
+        auto run_phase = [&](bool do_glu, int qg, bool do_cell, int qc, const PosInfo &pc, auto HZ, auto VT) __attribute__((always_inline)) {
+            constexpr bool hz = decltype(HZ)::value, vt = decltype(VT)::value;
+            const bool vt_prev = vt && pc.pos_vt == qc - 1;
+            if (REGW) {
+                auto gblock = [&](int rb, f32x4_t *acc2) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int c = 0; c < 2 * UB; c++) acc2[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kq = 0; kq < NKG; kq++) {
+                        const uint4 af = glu_frag(qg, rb, kq * KS);
+#pragma unroll
+                        for (int g = 0; g < 2; g++)
+#pragma unroll
+                            for (int ub = 0; ub < UB; ub++)
+                                P::mma(acc2[g * UB + ub], wgl[REGW ? g : 0][REGW ? kq : 0][REGW ? ub : 0], af);
+                    }
+                };
+                auto cblock = [&](int rb, f32x4_t *acc) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int c = 0; c < 3 * UB; c++) acc[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < NKS; ks++) {
+                        const int blk = ks / NKB;
+                        const bool is_x = ks == NKS - 1;
+                        if (!is_x && blk == 0 && !hz) continue;
+                        if (!is_x && blk == 1 && !vt) continue;
+                        const uint4 af = a_frag(qc, vt_prev, rb, ks);
+#pragma unroll
+                        for (int g = 0; g < 3; g++)
+#pragma unroll
+                            for (int ub = 0; ub < UB; ub++)
+                                P::mma(acc[g * UB + ub],
+                                       __builtin_bit_cast(uint4, wreg[REGW ? g : 0][REGW ? ks : 0][REGW ? ub : 0]), af);
+                    }
+                };
+                f32x4_t accg[2][2 * UB], accc[2][3 * UB];
+                if (do_glu) {
+                    gblock(0, accg[0]);
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++) {
+                        if (rb + 1 < RB) gblock(rb + 1, accg[(rb + 1) & 1]);
+                        else if (do_cell) cblock(0, accc[0]);
+                        glu_epi(qg, rb, accg[rb & 1]);
+                    }
+                } else if (do_cell) {
+                    cblock(0, accc[0]);
+                }
+                if (do_cell) {
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++) {
+                        if (rb + 1 < RB) cblock(rb + 1, accc[(rb + 1) & 1]);
+                        cell_epi(qc, pc, rb, accc[rb & 1]);
+                    }
+                }
+            } else {
+                if (do_glu) {
+                    f32x4_t acc2[RB][2 * UB];
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                        for (int c = 0; c < 2 * UB; c++) acc2[rb][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+                    for (int kk = 0; kk < KHB; kk += KS) {
+                        uint4 af[RB];
+#pragma unroll
+                        for (int rb = 0; rb < RB; rb++) af[rb] = glu_frag(qg, rb, kk);
+#pragma unroll
+                        for (int g = 0; g < 2; g++)
+#pragma unroll
+                            for (int ub = 0; ub < UB; ub++) {
+                                const int n = g * DH + wu * C::UW + ub * 16 + l16;
+                                const uint4 bf = *(const uint4 *)&Bg[(int64_t)n * KHB + kk + VEC * lq];
+#pragma unroll
+                                for (int rb = 0; rb < RB; rb++) P::mma(acc2[rb][g * UB + ub], bf, af[rb]);
+                            }
+                    }
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++) glu_epi(qg, rb, acc2[rb]);
+                }
+                if (do_cell) {
+                    f32x4_t acc[RB][3 * UB];
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                        for (int c = 0; c < 3 * UB; c++) acc[rb][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+                    for (int ks = 0; ks < NKS; ks++) {
+                        const int blk = ks / NKB;
+                        const bool is_x = ks == NKS - 1;
+                        if (!is_x && blk == 0 && !hz) continue;
+                        if (!is_x && blk == 1 && !vt) continue;
+                        uint4 af[RB];
+#pragma unroll
+                        for (int rb = 0; rb < RB; rb++) af[rb] = a_frag(qc, vt_prev, rb, ks);
+#pragma unroll
+                        for (int g = 0; g < 3; g++)
+#pragma unroll
+                            for (int ub = 0; ub < UB; ub++) {
+                                const int n = g * DH + wu * C::UW + ub * 16 + l16;
+                                const uint4 bf = *(const uint4 *)&Bc[(int64_t)n * KPX + ks * KS + VEC * lq];
+#pragma unroll
+                                for (int rb = 0; rb < RB; rb++) P::mma(acc[rb][g * UB + ub], bf, af[rb]);
+                            }
+                    }
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++) cell_epi(qc, pc, rb, acc[rb]);
+                }
+            }
+        };
+        using T1 = std::integral_constant<bool, true>;
+        using T0 = std::integral_constant<bool, false>;
+        auto phase = [&](bool do_glu, int qg, bool do_cell, int qc, const PosInfo &pc) __attribute__((always_inline)) {
+            const bool hz = pc.site_hz >= 0, vt = DIMS == 2 && pc.site_vt >= 0;
+            if (!do_cell || (!hz && !vt)) run_phase(do_glu, qg, do_cell, qc, pc, T0{}, T0{});
+            else if (DIMS == 1 || !vt) run_phase(do_glu, qg, do_cell, qc, pc, T1{}, T0{});
+            else if (hz) run_phase(do_glu, qg, do_cell, qc, pc, T1{}, T1{});
+            else run_phase(do_glu, qg, do_cell, qc, pc, T0{}, T1{});
+        };
+
+        // per-row finalisation of position qf (owner lanes): log-softmax, the
+        // sampling decision or the given spin, FP64 accumulation
+        auto finalize = [&](int qf, const PosInfo &pi) __attribute__((always_inline)) {
+            if (!owner || my_s < 0) return;
+            const int r = orow, s = my_s, lb = qf % C::NLOG;
+            float l0 = hc0, l1 = hc1, z0 = hc2, z1 = hc3;
+#pragma unroll
+            for (int x = 0; x < C::WU; x++) {
+                const float4 v = *(const float4 *)&sLog[lb][x][r][0];
+                l0 += v.x;
+                l1 += v.y;
+                z0 += v.z;
+                z1 += v.w;
+            }
+            const float mx = fmaxf(l0, l1);
+            const float lse = mx + __logf(1.0f + __expf(-fabsf(l0 - l1)));
+            const float ls0 = l0 - lse, ls1 = l1 - lse;
+            const float ph0 = cplx ? PI_F * softsignf_(z0) : 0.f;
+            const float ph1 = cplx ? PI_F * softsignf_(z1) : 0.f;
+            int sg;
+            if (mode == MODE_SAMPLE) {
+                float uni;
+                if (a.uniforms) {
+                    uni = a.uniforms[(int64_t)s * N + qf];
+                } else {
+                    uint32_t c4[4] = {(uint32_t)(qf >> 2), (uint32_t)s, (uint32_t)a.counter,
+                                      (uint32_t)(a.counter >> 32)};
+                    philox4x32_10(c4, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+                    const uint32_t wsel =
+                        (qf & 3) == 0 ? c4[0] : (qf & 3) == 1 ? c4[1] : (qf & 3) == 2 ? c4[2] : c4[3];
+                    uni = (float)(wsel >> 8) * (1.0f / 16777216.0f);
+                }
+                sg = (uni < __expf(ls0)) ? 0 : 1;
+                sSig[r * N + pi.site] = (uint8_t)sg;
+            } else {
+                sg = sSig[r * N + pi.site];
+            }
+            acc_lp += (double)(sg ? ls1 : ls0);
+            acc_ph += (double)(sg ? ph1 : ph0);
+            if (store_lpc) {
+                *(float2 *)&a.lpc[((int64_t)s * N + qf) * 2] = make_float2(ls0, ls1);
+                *(float2 *)&a.phc[((int64_t)s * N + qf) * 2] = make_float2(ph0, ph1);
+                a.pre[(int64_t)s * N + qf] = make_double2(acc_lp, acc_ph);
+            }
+            if (store_act) {
+                float *lg = a.lgT + (int64_t)qf * 4 * a.nsp + s;
+                lg[0] = l0;
+                lg[a.nsp] = l1;
+                lg[2 * a.nsp] = z0;
+                lg[3 * a.nsp] = z1;
+            }
+        };
+
+        // ------------------------------------------------------ site loop
+        if (TF) {
+            const int q0 = p + 1;
+            const PosInfo P0 = pos(q0);
+            if (vt_needed(q0, P0)) {
+                vt_issue(P0);
+                vt_store(q0 & 1);
+            }
+            indicator(P0, q0 & 1);
+            if (q0 + 1 < N) {
+                const PosInfo P1 = pos(q0 + 1);
+                if (vt_needed(q0 + 1, P1)) {
+                    vt_issue(P1);
+                    vt_store((q0 + 1) & 1);
+                }
+                indicator(P1, (q0 + 1) & 1);
+            }
+            __syncthreads();
+            phase(false, q0, true, q0, P0);
+            __syncthreads();
+            PosInfo Pc = P0, Pp = P0;
+            for (int q = q0; q < N; q++) {
+                const bool has_next = q + 1 < N, has_2 = q + 2 < N;
+                const PosInfo Pn = has_next ? pos(q + 1) : Pc;
+                const PosInfo P2 = has_2 ? pos(q + 2) : Pc;
+                const bool vt2 = has_2 && vt_needed(q + 2, P2);
+                if (vt2) vt_issue(P2);
+                if (Pc.colw) col_copy(q, Pc);
+                phase(glu, q, has_next, q + 1, Pn);
+                if (has_2) {
+                    if (vt2) vt_store(q & 1);
+                    indicator(P2, q & 1);
+                }
+                if (q > q0) finalize(q - 1, Pp);
+                __syncthreads();
+                Pp = Pc;
+                Pc = Pn;
+            }
+            finalize(N - 1, Pp);
+            __syncthreads();
+        } else {
+            PosInfo Pc = pos(0);
+            indicator(Pc, 0);
+            __syncthreads();
+            for (int q = 0; q < N; q++) {
+                const bool has_next = q + 1 < N;
+                const PosInfo Pn = has_next ? pos(q + 1) : Pc;
+                const bool vtn = has_next && vt_needed(q + 1, Pn);
+                if (vtn) vt_issue(Pn);
+                phase(false, q, true, q, Pc);
+                if (vtn) vt_store((q + 1) & 1);
+                __syncthreads();
+                if (Pc.colw) col_copy(q, Pc);
+                if (glu) phase(true, q, false, q, Pc);
+                __syncthreads();
+                finalize(q, Pc);
+                if (has_next) indicator(Pn, (q + 1) & 1);
+                __syncthreads();
+                Pc = Pn;
+            }
+        }
+
+        // ------------------------------------------------------ tile outputs
+        if (owner && my_s >= 0) {
+            if (mode == MODE_CHAIN) {
+                a.dsuf[(int64_t)my_s * a.NC + cidx] = make_double2(acc_lp, acc_ph);
+            } else {
+                if (a.logp) a.logp[my_s] = (float)acc_lp;
+                if (a.phase) a.phase[my_s] = (float)acc_ph;
+            }
+        }
+        if (mode == MODE_SAMPLE) {
+            for (int e = tid; e < MT * N; e += NT) {
+                const int r = e / N, c = e - r * N;
+                const int s = sRow[r];
+                if (s >= 0) a.cfg_out[(int64_t)s * N + c] = sSig[e];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF>
+static hipError_t launch_engine_s(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
+    typedef Eng<P, DIMS, DH, NW> C;
+    size_t dyn = ((size_t)C::MT * a.d.N + 15) / 16 * 16;
+    hipError_t e = hipFuncSetAttribute((const void *)rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF>), dim3(grid), dim3(NW * 64), dyn, st, a, mode,
+                       sh, sl, sa);
+    return hipGetLastError();
+}
+
+template <class P, int DIMS, int DH, int NW, int REGW>
+static hipError_t launch_engine_t(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
+    const bool store = sh || sl || sa, tf = mode != MODE_SAMPLE;
+    if (store)
+        return tf ? launch_engine_s<P, DIMS, DH, NW, REGW, 1, 1>(a, mode, sh, sl, sa, grid, st)
+                  : launch_engine_s<P, DIMS, DH, NW, REGW, 1, 0>(a, mode, sh, sl, sa, grid, st);
+    return tf ? launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1>(a, mode, sh, sl, sa, grid, st)
+              : launch_engine_s<P, DIMS, DH, NW, REGW, 0, 0>(a, mode, sh, sl, sa, grid, st);
+}
+
+// Variant per precision and width: bfloat16 up to d_h = 128 keeps the
+// weights in registers (8 waves at 128, 4 below); the rest stream from L2.
+template <class P, int DH>
+struct Pick {
+    static constexpr int REGW = (P::VEC == 8 && DH <= 128) ? 1 : 0;
+    static constexpr int NW = (REGW && DH == 128) ? 8 : 4;
+};
+
+template <class P, int DIMS>
+static hipError_t launch_engine_d(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
+#define VMC_ENG(DHV) \
+    launch_engine_t<P, DIMS, DHV, Pick<P, DHV>::NW, Pick<P, DHV>::REGW>(a, mode, sh, sl, sa, grid, st)
+    switch (a.d.DH) {
+        case 16: return VMC_ENG(16);
+        case 32: return VMC_ENG(32);
+        case 64: return VMC_ENG(64);
+        case 128: return VMC_ENG(128);
+        case 256: return VMC_ENG(256);
+    }
+#undef VMC_ENG
+    return hipErrorInvalidValue;
+}
+
+template <class P, int DIMS>
+static size_t engine_lds_d(int DH, int N) {
+#define VMC_LDS(DHV) Eng<P, DIMS, DHV, Pick<P, DHV>::NW>::LDS + (size_t)Eng<P, DIMS, DHV, 4>::MT * N
+    switch (DH) {
+        case 16: return VMC_LDS(16);
+        case 32: return VMC_LDS(32);
+        case 64: return VMC_LDS(64);
+        case 128: return VMC_LDS(128);
+        case 256: return VMC_LDS(256);
+    }
+#undef VMC_LDS
+    return (size_t)1 << 30;
+}
+
+}  // namespace vmc

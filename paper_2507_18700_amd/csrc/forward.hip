@@ -157,6 +157,35 @@ __global__ void stage_weights(Dims d, const float *__restrict__ prm, typename P:
     }
 }
 
+// Facts of each order position q of the chain, one int4:
+//   x = site | colw << 16   (colw: h(q) is the vertical input of a later,
+//                            non-row-start position of its column)
+//   y = site of the horizontal predecessor q-1 (-1 at a row start)
+//   z = site of the vertical predecessor (2D, -1 in the first row)
+//   w = (position of the vertical predecessor + 1) | column << 16
+__global__ void build_postab(Dims d, int4 *tab) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= d.N) return;
+    const int Lx = d.Lx, Ly = d.Ly;
+    int site, shz, svt = -1, pvt = -1, icol, colw = 0;
+    if (d.dims == 1) {
+        site = q;
+        shz = q > 0 ? q - 1 : -1;
+        icol = q;
+    } else {
+        const int j = q / Lx, k = q - j * Lx;
+        site = order_site(q, Lx);
+        icol = site - j * Lx;
+        shz = k > 0 ? order_site(q - 1, Lx) : -1;
+        if (j > 0) {
+            svt = site - Lx;
+            pvt = site_pos(svt, Lx);
+        }
+        colw = (j + 1 < Ly) && ((q + 1) % Lx != 0);
+    }
+    tab[q] = make_int4(site | (colw << 16), shz, svt, (pvt + 1) | (icol << 16));
+}
+
 // --------------------------------------------------------- chain schedule
 
 // Per first-changed position p: capacity offsets of the connection list
@@ -280,7 +309,8 @@ __global__ void eloc_assemble(int ham_kind, int marshall, double J, double hx, i
 int engine_kpx(const Dims &d);
 
 hipError_t launch_stage(const Dims &d, const float *prm, void *Bc, void *BcT, void *Bg, void *BgT,
-                        float *E, float *Hd, float *hc, hipStream_t st) {
+                        float *E, float *Hd, float *hc, int4 *postab, hipStream_t st) {
+    hipLaunchKernelGGL(build_postab, dim3((d.N + 255) / 256), dim3(256), 0, st, d, postab);
     const int ks = d.prec == VMC_BF16 ? 32 : 16;
     const int KHB = cround(d.DH, ks), NCP = cround(3 * d.DH, ks), KPX = engine_kpx(d);
     const int NHB = d.dims == 1 ? 1 : 2;

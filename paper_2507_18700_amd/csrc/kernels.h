@@ -20,6 +20,8 @@ struct FwdArgs {
     float *logp, *phase;     // SAMPLE/LOGPSI, may be NULL
     // caches (NULL = not written / not read)
     float *hcache;           // [N][ns][DH] fp32 hidden states
+    void *hcs;               // [N][ns][DH] hidden states as MFMA operands (store_t; FP32: = hcache)
+    const int4 *postab;      // [N] facts of each order position (build_postab)
     float *lpc, *phc;        // [ns][N][2] log-conditionals, phase conditionals
     double2 *pre;            // [ns][N] running (log P, phase) after each position, FP64
     float *act;              // [N][NF*DH][nsp] gate and GLU pre-activations for the backward (FP32)
