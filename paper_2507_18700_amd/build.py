@@ -13,8 +13,18 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvmcrnn.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "engine.hip", "engine_bf16_1d.hip", "engine_bf16_2d.hip", "engine_f32_1d.hip",
-           "engine_f32_2d.hip", "backward.hip", "forward.hip", "grad.hip", "grow.hip"]
+SOURCES = [
+    "api.hip",
+    "engine.hip",
+    "engine_bf16_1d.hip",
+    "engine_bf16_2d.hip",
+    "engine_f32_1d.hip",
+    "engine_f32_2d.hip",
+    "backward.hip",
+    "forward.hip",
+    "grad.hip",
+    "grow.hip",
+]
 ARCH = "gfx950"
 
 
@@ -23,15 +33,15 @@ def hipcc():
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def _flags():
+def _flags(csrc):
     return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
             "-Wno-unused-variable", "-Wno-unused-but-set-variable", "-I" + os.path.join(ROOT, "include"),
-            "-I" + CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+            "-I" + csrc, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + _flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src, csrc=CSRC, build_dir=BUILD):
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc()] + _flags(csrc) + ["-c", os.path.join(csrc, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -39,21 +49,22 @@ def _compile(src):
     return obj, out
 
 
-def build(verbose=False):
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose=False, csrc=CSRC, lib=LIB, build_dir=BUILD):
+    """Compile every source of `csrc` and link `lib` (defaults: the package)."""
+    os.makedirs(build_dir, exist_ok=True)
     jobs = int(os.environ.get("MAX_JOBS", "8"))
     with concurrent.futures.ThreadPoolExecutor(max_workers=max(1, min(jobs, len(SOURCES)))) as ex:
-        results = list(ex.map(_compile, SOURCES))
+        results = list(ex.map(lambda src: _compile(src, csrc, build_dir), SOURCES))
     objs = [o for o, _ in results]
     if verbose:
         for _, out in results:
             if out.strip():
                 print(out)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -11,7 +11,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvmcrnn.so")
+# the in-tree build; VMCRNN_LIB names another build of the same sources
+LIB_PATH = os.environ.get("VMCRNN_LIB") or os.path.join(_HERE, "libvmcrnn.so")
 
 VMC_FP32, VMC_BF16 = 0, 1
 VMC_TFIM, VMC_HEISENBERG = 0, 1
