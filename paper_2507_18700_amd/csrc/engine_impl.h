@@ -48,7 +48,6 @@ struct Eng {
     static constexpr int MT = (DH >= 256 || (P::VEC == 4 && DH >= 128)) ? 32 : 64;
     static constexpr int RW = MT / WR;
     static constexpr int RB = RW / 16;
-    static constexpr int FR = MT / NW;                         // rows finalised per wave
     static constexpr int KS = P::KSTEP;
     static constexpr int KHB = cround(DH, KS);                 // one hidden block of the operand
     static constexpr int NKB = KHB / KS;                       // k-steps per hidden block
@@ -62,7 +61,7 @@ struct Eng {
     // static LDS of the kernel (bytes), for the host-side capacity check
     static constexpr size_t LDS =
         sizeof(typename P::store_t) * ((size_t)2 * MT * H_LD + (DIMS == 2 ? 2 * MT * H_LD : 8) + 2 * MT * X_LD) +
-        4 * ((size_t)NLOG * WU * MT * 4 + 2 * DH) + 4 * MT + 16;
+        4 * ((size_t)NLOG * WU * MT * 4 + 2 * DH) + 8 * MT + 16 * MT + 16;
 };
 
 // Sum over the four 16-lane groups of a wave (lanes l, l^16, l^32, l^48);
@@ -109,7 +108,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     const int store_h = STORE && store_h_, store_lpc = STORE && store_lpc_, store_act = STORE && store_act_;
     typedef Eng<P, DIMS, DH, NW> C;
     typedef typename P::store_t T;
-    constexpr int MT = C::MT, RB = C::RB, UB = C::UB, KS = C::KS, VEC = P::VEC, FR = C::FR;
+    constexpr int MT = C::MT, RB = C::RB, UB = C::UB, KS = C::KS, VEC = P::VEC;
     constexpr int KHB = C::KHB, NKB = C::NKB, NKS = C::NKS, KPX = C::KPX;
     constexpr int H_LD = C::H_LD, X_LD = C::X_LD, NT = NW * 64;
     constexpr int NKG = KHB / KS;          // k-steps of the GLU contraction
@@ -121,7 +120,8 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     __shared__ __align__(16) T sX[2][MT * X_LD];
     __shared__ __align__(16) float sLog[C::NLOG][C::WU][MT][4];
     __shared__ __align__(16) float sHw[2][DH];  // phase-head rows (complex amplitudes)
-    __shared__ int sRow[MT];
+    __shared__ int sRow[MT], sCid[MT];
+    __shared__ double2 sAcc[MT];  // running (log P, phase) of each row, FP64
     __shared__ int sTile;
     extern __shared__ uint8_t sSig[];  // [MT][N]
 
@@ -136,9 +136,6 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     const int64_t ns_c = a.ns_cache;
     T *colbuf = (T *)a.colbuf + (int64_t)blockIdx.x * Lx * MT * DH;
     const int l16 = lane & 15, lq = lane >> 4;
-    // row finalised by this lane (FR rows per wave)
-    const bool owner = lane < FR;
-    const int orow = w * FR + lane;
     auto unit0 = [&](int ub) __attribute__((always_inline)) { return wu * C::UW + ub * 16 + 4 * lq; };
 
     // per-lane constants of this lane's units: GLU biases, amplitude head
@@ -262,10 +259,10 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
         first = false;
 
         // ------------------------------------------------------ row setup
-        int my_s = -1, f1 = -1, f2 = -1, cidx = 0;  // of row orow (owner lanes)
-        if (owner) {
-            if (orow < nrow) {
-                const int64_t ent = e0 + orow;
+        int my_s = -1, f1 = -1, f2 = -1, cidx = 0;  // of row tid (tid < MT)
+        if (tid < MT) {
+            if (tid < nrow) {
+                const int64_t ent = e0 + tid;
                 if (mode != MODE_CHAIN) {
                     my_s = (int)ent;
                 } else if (a.ham_kind == 0) {
@@ -279,7 +276,9 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                     bond_sites(cidx, Lx, Ly, f1, f2);
                 }
             }
-            sRow[orow] = my_s;
+            sRow[tid] = my_s;
+            sCid[tid] = cidx;
+            sAcc[tid] = make_double2(0.0, 0.0);
         }
         __syncthreads();
         for (int e = tid; e < MT * N; e += NT) {
@@ -288,10 +287,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             sSig[e] = (s >= 0 && mode != MODE_SAMPLE) ? a.cfg_in[(int64_t)s * N + c] : (uint8_t)0;
         }
         __syncthreads();
-        if (owner && my_s >= 0 && mode == MODE_CHAIN) {
-            sSig[orow * N + f1] ^= 1;
-            if (f2 >= 0) sSig[orow * N + f2] ^= 1;
+        if (tid < MT && my_s >= 0 && mode == MODE_CHAIN) {
+            sSig[tid * N + f1] ^= 1;
+            if (f2 >= 0) sSig[tid * N + f2] ^= 1;
         }
+        __syncthreads();
         // previous hidden state of the first step: h(p) from the prefix cache
         float hreg[DIMS == 1 ? RB : 1][DIMS == 1 ? UB : 1][4];
 #pragma unroll
@@ -325,7 +325,6 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 }
             }
         }
-        double acc_lp = 0.0, acc_ph = 0.0;
 
         // -------------------------------------------------- phase pieces
         // vertical input rows of a position (2D, not the row start): from the
@@ -368,10 +367,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 *(uint4 *)&colbuf[((int64_t)pi.icol * MT + r) * DH + c] = *(const uint4 *)&sH[qn & 1][r * H_LD + c];
             }
         };
-        // indicator columns of position qn for the owned row (one 16-byte store):
+        // indicator columns of position qn, one row per lane of wave iw (one 16-byte store):
         // FP32 [x_hz0, x_hz1, x_vt0, x_vt1]; BF16 each twice (hi, lo)
-        auto indicator = [&](const PosInfo &pi, int buf) __attribute__((always_inline)) {
-            if (!owner) return;
+        auto indicator = [&](const PosInfo &pi, int buf, int iw) __attribute__((always_inline)) {
+            if (w != iw || lane >= MT) return;
+            const int orow = lane;
             const int xz = pi.site_hz >= 0 ? sSig[orow * N + pi.site_hz] : -1;
             const int xv = pi.site_vt >= 0 ? sSig[orow * N + pi.site_vt] : -1;
             const uint32_t one = VEC == 8 ? 0x3F803F80u : 0x3F800000u;
@@ -610,11 +610,13 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             else run_phase(do_glu, qg, do_cell, qc, pc, T0{}, T1{});
         };
 
-        // per-row finalisation of position qf (owner lanes): log-softmax, the
-        // sampling decision or the given spin, FP64 accumulation
-        auto finalize = [&](int qf, const PosInfo &pi) __attribute__((always_inline)) {
-            if (!owner || my_s < 0) return;
-            const int r = orow, s = my_s, lb = qf % C::NLOG;
+        // per-row finalisation of position qf, one row per lane of wave fw:
+        // log-softmax, the sampling decision or the given spin, FP64
+        // accumulation
+        auto finalize = [&](int qf, const PosInfo &pi, int fw) __attribute__((always_inline)) {
+            if (w != fw || lane >= MT) return;
+            const int r = lane, s = sRow[r], lb = qf % C::NLOG;
+            if (s < 0) return;
             float l0 = hc0, l1 = hc1, z0 = hc2, z1 = hc3;
 #pragma unroll
             for (int x = 0; x < C::WU; x++) {
@@ -647,12 +649,14 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             } else {
                 sg = sSig[r * N + pi.site];
             }
-            acc_lp += (double)(sg ? ls1 : ls0);
-            acc_ph += (double)(sg ? ph1 : ph0);
+            double2 acc = sAcc[r];
+            acc.x += (double)(sg ? ls1 : ls0);
+            acc.y += (double)(sg ? ph1 : ph0);
+            sAcc[r] = acc;
             if (store_lpc) {
                 *(float2 *)&a.lpc[((int64_t)s * N + qf) * 2] = make_float2(ls0, ls1);
                 *(float2 *)&a.phc[((int64_t)s * N + qf) * 2] = make_float2(ph0, ph1);
-                a.pre[(int64_t)s * N + qf] = make_double2(acc_lp, acc_ph);
+                a.pre[(int64_t)s * N + qf] = acc;
             }
             if (store_act) {
                 float *lg = a.lgT + (int64_t)qf * 4 * a.nsp + s;
@@ -671,14 +675,14 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 vt_issue(P0);
                 vt_store(q0 & 1);
             }
-            indicator(P0, q0 & 1);
+            indicator(P0, q0 & 1, 0);
             if (q0 + 1 < N) {
                 const PosInfo P1 = pos(q0 + 1);
                 if (vt_needed(q0 + 1, P1)) {
                     vt_issue(P1);
                     vt_store((q0 + 1) & 1);
                 }
-                indicator(P1, (q0 + 1) & 1);
+                indicator(P1, (q0 + 1) & 1, NW / 2);
             }
             __syncthreads();
             phase(false, q0, true, q0, P0);
@@ -694,18 +698,18 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 phase(glu, q, has_next, q + 1, Pn);
                 if (has_2) {
                     if (vt2) vt_store(q & 1);
-                    indicator(P2, q & 1);
+                    indicator(P2, q & 1, (q + 2 + NW / 2) % NW);
                 }
-                if (q > q0) finalize(q - 1, Pp);
+                if (q > q0) finalize(q - 1, Pp, (q - 1) % NW);
                 __syncthreads();
                 Pp = Pc;
                 Pc = Pn;
             }
-            finalize(N - 1, Pp);
+            finalize(N - 1, Pp, (N - 1) % NW);
             __syncthreads();
         } else {
             PosInfo Pc = pos(0);
-            indicator(Pc, 0);
+            indicator(Pc, 0, 0);
             __syncthreads();
             for (int q = 0; q < N; q++) {
                 const bool has_next = q + 1 < N;
@@ -718,20 +722,23 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 if (Pc.colw) col_copy(q, Pc);
                 if (glu) phase(true, q, false, q, Pc);
                 __syncthreads();
-                finalize(q, Pc);
-                if (has_next) indicator(Pn, (q + 1) & 1);
+                // the row's lane draws its spin and writes the next indicator
+                finalize(q, Pc, q % NW);
+                if (has_next) indicator(Pn, (q + 1) & 1, q % NW);
                 __syncthreads();
                 Pc = Pn;
             }
         }
 
         // ------------------------------------------------------ tile outputs
-        if (owner && my_s >= 0) {
+        if (tid < MT && sRow[tid] >= 0) {
+            const int s = sRow[tid];
+            const double2 acc = sAcc[tid];
             if (mode == MODE_CHAIN) {
-                a.dsuf[(int64_t)my_s * a.NC + cidx] = make_double2(acc_lp, acc_ph);
+                a.dsuf[(int64_t)s * a.NC + sCid[tid]] = acc;
             } else {
-                if (a.logp) a.logp[my_s] = (float)acc_lp;
-                if (a.phase) a.phase[my_s] = (float)acc_ph;
+                if (a.logp) a.logp[s] = (float)acc.x;
+                if (a.phase) a.phase[s] = (float)acc.y;
             }
         }
         if (mode == MODE_SAMPLE) {
