@@ -22,6 +22,7 @@ FWD_CASES = [
     (2, 6, 6, 64, False, True),
     (2, 4, 3, 128, True, True),
     (1, 9, 1, 130, False, True),    # d_h padded 130 -> 256
+    (2, 3, 4, 200, True, True),     # 2D, d_h padded 200 -> 256
 ]
 
 
@@ -114,6 +115,7 @@ ELOC_CASES = [
     (2, 3, 4, 20, True, True, "heis", 0.0),
     (2, 4, 3, 64, False, True, "heis", 0.0),
     (2, 3, 3, 128, False, True, "tfim", 3.0),
+    (2, 3, 3, 256, True, True, "heis", 0.0),   # d_h = 256 with phases (the 2D Heisenberg width)
 ]
 
 
