@@ -15,6 +15,7 @@ suffix-chain launch of local_energy), timed with HIP events on its stream;
 `cpu_baseline` is the FP64 oracle on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,6 +31,48 @@ DH0, DH = 64, 128
 NS = 10000
 H_FIELD, J_COUP = 3.0, 1.0
 PEAK_TF = {"bf16": 2500.0, "fp32": 157.3}
+
+
+# HBM traffic of the chain kernel, measured with rocprofv3 counters
+# (FETCH_SIZE, WRITE_SIZE, scaled by the same counters on a plain copy of
+# known size); valid only for the engine sources it was measured on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rnn_engine_chain_tfim2d_10x10_dh128_bf16.json")
+ENGINE_SOURCES = ["engine_impl.h", "engine.hip", "engine_bf16_2d.hip", "common.h", "kernels.h"]
+
+
+def engine_source_hash():
+    h = hashlib.sha256()
+    for f in ENGINE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2507_18700_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """Bytes per chain launch from the committed counter summary, or None if
+    it was taken on other engine sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return t.get("bytes_per_launch") if t.get("engine_source_hash") == engine_source_hash() else None
+
+
+def copy_calibration(nbytes):
+    """A plain device copy of known size (the counter calibration run)."""
+    import torch
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3, "ms_last": round(dt * 1e3, 3),
+                      "engine_source_hash": engine_source_hash()}))
 
 
 def site_flops(dh, n_out=2):
@@ -110,14 +153,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-samples", type=int, default=192)
+    ap.add_argument("--cpu-samples", type=int, default=768)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_bytes:
+        copy_calibration(args.copy_bytes)
+        return
     import torch
     from paper_2507_18700_amd import synth, vmcrnn as V
     if not torch.cuda.is_available():
@@ -155,9 +203,9 @@ def main():
                                "d_h 64->128 via grow_hidden; Ns=10000 per step; sample + E_loc + grad",
                    "Lx": LX, "Ly": LY, "d_h": DH, "ns": NS, "precision": "bf16 MFMA operands, fp32 accumulate, "
                                                                          "fp64 cross-sample reductions"},
-        "roofline": {"bound": "mfma", "kernel": "rnn_forward<BF16,2,128> (suffix chains of local_energy)",
+        "roofline": {"bound": "mfma", "kernel": "rnn_engine<BF16,2,128> chain launch (suffix chains of local_energy)",
                      "achieved": round(achieved, 2), "peak": PEAK_TF["bf16"], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_TF["bf16"], 4), "traffic": None,
+                     "frac": round(achieved / PEAK_TF["bf16"], 4), "traffic": measured_traffic(),
                      "flops_per_launch": flops_chain, "avg_launch_ms": round(bf["chain_ms"], 3)},
         "step_flops_algorithmic": flops_step,
         "step_frac_of_bf16_peak": round(flops_step / (bf["ms_per_step"] * 1e-3) / 1e12 / PEAK_TF["bf16"], 4),
