@@ -129,6 +129,18 @@ vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const u
                     const double *eloc, const double *weights, double *grad, double *stats,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* Vector-Jacobian product of rnn_logpsi (the backward of log psi as a
+ * differentiable function of the parameters, Eq. 1 through App. A):
+ *   grad[k] = sum_s ( dlogp[s] * d logP(sigma_s)/d theta_k
+ *                   + dphase[s] * d phi(sigma_s)/d theta_k ),
+ * logP = log |psi|^2 and phi the phase (Eqs. 3-5).  dlogp [nc] float32
+ * (required), dphase [nc] float32 or NULL (= 0; ignored for a positive RNN),
+ * grad [P] float64 (overwritten).  Same reverse sweep as vmc_grad, with the
+ * per-sample coefficients given instead of formed from the local energies. */
+vmc_status rnn_logpsi_grad(const vmc_model *m, const float *params, int64_t nc, const uint8_t *configs,
+                           const float *dlogp, const float *dphase, double *grad, void *ws, size_t ws_bytes,
+                           void *stream);
+
 /* One VMC step in one call: rnn_sample, then local_energy of the samples,
  * then vmc_grad with w_s = 1/ns, sharing one forward pass (the sampler keeps
  * the hidden states, conditionals and activations that the local energy and

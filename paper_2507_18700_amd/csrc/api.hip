@@ -310,7 +310,7 @@ static vmc_status eloc_from_cache(const Dims &d, const WsMap &w, void *ws, const
 // configurations.
 static vmc_status grad_from_cache(const Dims &d, const WsMap &w, void *ws, int64_t ns, const uint8_t *configs,
                                   const double *eloc, const double *weights, double *grad, double *stats,
-                                  hipStream_t st) {
+                                  hipStream_t st, const float *coef_lp = NULL, const float *coef_ph = NULL) {
     GradBufs b;
     b.d = d;
     b.BcT = at<void>(ws, w.BcT);
@@ -324,6 +324,8 @@ static vmc_status grad_from_cache(const Dims &d, const WsMap &w, void *ws, int64
     b.lgT = at<float>(ws, w.lgT);
     b.eloc = eloc;
     b.weights = weights;
+    b.coef_lp = coef_lp;
+    b.coef_ph = coef_ph;
     b.stats = stats ? stats : at<double>(ws, w.stats);
     b.dtc = at<void>(ws, w.dtc);
     b.dtg = at<void>(ws, w.dtg);
@@ -384,6 +386,30 @@ vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const u
     e = launch_forward(a, MODE_LOGPSI, 1, 0, 1, w.fwd_grid, st);
     if (e != hipSuccess) return VMC_EDEVICE;
     return grad_from_cache(d, w, ws, ns, configs, eloc, weights, grad, stats, st);
+}
+
+vmc_status rnn_logpsi_grad(const vmc_model *m, const float *params, int64_t nc, const uint8_t *configs,
+                           const float *dlogp, const float *dphase, double *grad, void *ws, size_t ws_bytes,
+                           void *stream) {
+    vmc_status s = check_common(m, params, nc, ws, ws_bytes, NULL, NULL);
+    if (s != VMC_OK) return s;
+    if (!configs || !dlogp || !grad) return VMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Dims d = make_dims(m);
+    WsMap w = ws_map(d, NULL, nc);
+    hipError_t e = stage(d, params, ws, w, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    FwdArgs a = base_args(d, ws, w, nc);
+    a.cfg_in = configs;
+    a.hcache = at<float>(ws, w.hcache);
+    a.act = at<float>(ws, w.act);
+    a.lgT = at<float>(ws, w.lgT);
+    a.hT = at<void>(ws, w.hT);
+    a.gT = at<void>(ws, w.gT);
+    a.nsp = w.nsp;
+    e = launch_forward(a, MODE_LOGPSI, 1, 0, 1, w.fwd_grid, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    return grad_from_cache(d, w, ws, nc, configs, NULL, NULL, grad, NULL, st, dlogp, d.cplx ? dphase : NULL);
 }
 
 vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns, uint64_t seed,

@@ -3,7 +3,8 @@
 //
 // With E held constant the gradient is that of
 //   L = sum_s [a_s log P(sigma_s) + b_s phi(sigma_s)],
-//   a_s = w_s Re(E_s - Ebar), b_s = 2 w_s Im(E_s - Ebar).
+//   a_s = w_s Re(E_s - Ebar), b_s = 2 w_s Im(E_s - Ebar),
+// or, for the vector-Jacobian product of log psi, with a_s, b_s given.
 // At each order position, last to first:
 //   (a) head deltas: a_s (onehot(sigma) - softmax(l)) (Eq. 3) and
 //       b_s pi softsign'(z_sigma) (Eq. 5);
@@ -31,6 +32,7 @@ struct BwdArgs {
     const float *lgT;       // [N][4][nsp] logits
     const float *hcache;    // [N][ns][DH] FP32 hidden states (1D: h_{n-1} of the update-gate term)
     const double *eloc, *w, *stats;
+    const float *coef_lp, *coef_ph;  // given coefficients a_s, b_s (then eloc, w, stats are unused)
     void *dtc, *dtg, *dth;  // transposed deltas: cell [N][NDC][nsp], GLU [N][2DH][nsp], heads [N][4][nsp]
     float *dcol;            // [grid][Lx][MT][DH]
 };
@@ -121,9 +123,14 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
         sRow[tid] = s;
         float ca = 0.f, cb = 0.f;
         if (s >= 0) {
-            const double ws = a.w ? a.w[s] : 1.0 / (double)ns;
-            ca = (float)(ws * (a.eloc[2 * s] - a.stats[0]));
-            cb = (float)(2.0 * ws * (a.eloc[2 * s + 1] - a.stats[1]));
+            if (a.coef_lp) {
+                ca = a.coef_lp[s];
+                cb = a.coef_ph ? a.coef_ph[s] : 0.f;
+            } else {
+                const double ws = a.w ? a.w[s] : 1.0 / (double)ns;
+                ca = (float)(ws * (a.eloc[2 * s] - a.stats[0]));
+                cb = (float)(2.0 * ws * (a.eloc[2 * s + 1] - a.stats[1]));
+            }
         }
         sCoef[tid][0] = ca;
         sCoef[tid][1] = cb;
@@ -460,6 +467,8 @@ hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st) {
     a.eloc = b.eloc;
     a.w = b.weights;
     a.stats = b.stats;
+    a.coef_lp = b.coef_lp;
+    a.coef_ph = b.coef_ph;
     a.dtc = b.dtc;
     a.dtg = b.dtg;
     a.dth = b.dth;

@@ -309,7 +309,7 @@ hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st);
 
 hipError_t launch_grad(const GradBufs &b, hipStream_t st) {
     const Dims &d = b.d;
-    hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(1024), 0, st, b.ns, b.eloc, b.weights, b.stats);
+    if (!b.coef_lp) hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(1024), 0, st, b.ns, b.eloc, b.weights, b.stats);
     hipError_t e = launch_backward(b, grad_nsp(b.ns), st);
     if (e != hipSuccess) return e;
     {

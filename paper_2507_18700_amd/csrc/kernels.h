@@ -51,6 +51,7 @@ struct GradBufs {
     const uint8_t *cfg;
     const float *hcache, *act, *lgT;
     const double *eloc, *weights;
+    const float *coef_lp, *coef_ph;  // given per-sample coefficients (vector-Jacobian product), or NULL
     double *stats;
     void *dtc, *dtg, *dth;  // transposed deltas (cell, GLU, heads)
     const void *hT, *gT;    // transposed hidden states and GLU outputs

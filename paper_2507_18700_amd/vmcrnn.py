@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("VMCRNN_LIB") or os.path.join(_HERE, "libvmcrnn.so")
 VMC_FP32, VMC_BF16 = 0, 1
 VMC_TFIM, VMC_HEISENBERG = 0, 1
 
-EXPORTS = ("vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "local_energy",
+EXPORTS = ("vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "rnn_logpsi_grad", "local_energy",
            "vmc_grad", "vmc_step", "grow_hidden", "vmc_chain_timing", "vmc_chain_time", "vmc_status_str")
 
 
@@ -71,6 +71,8 @@ def lib():
         L.rnn_sample.argtypes = [P(Model), vp, i64, u64, u64, vp, vp, vp, vp, vp, sz, vp]
         L.rnn_logpsi.restype = ctypes.c_int
         L.rnn_logpsi.argtypes = [P(Model), vp, i64, vp, vp, vp, vp, sz, vp]
+        L.rnn_logpsi_grad.restype = ctypes.c_int
+        L.rnn_logpsi_grad.argtypes = [P(Model), vp, i64, vp, vp, vp, vp, vp, sz, vp]
         L.local_energy.restype = ctypes.c_int
         L.local_energy.argtypes = [P(Model), vp, P(Ham), i64, vp, vp, vp, sz, vp]
         L.vmc_grad.restype = ctypes.c_int
@@ -178,6 +180,49 @@ def rnn_logpsi(m, params, configs, ws=None):
     _check(lib().rnn_logpsi(ctypes.byref(m), _ptr(params), nc, _ptr(configs), _ptr(lp), _ptr(ph), _ptr(buf),
                             nb, _stream()))
     return lp, ph
+
+
+def rnn_logpsi_grad(m, params, configs, dlogp, dphase=None, ws=None, out=None):
+    """Vector-Jacobian product of rnn_logpsi: sum_s dlogp_s d logP_s + dphase_s d phi_s,
+    float64 [P]."""
+    _dev(params, torch.float32, "params")
+    _dev(configs, torch.uint8, "configs")
+    _dev(dlogp, torch.float32, "dlogp")
+    if dphase is not None:
+        _dev(dphase, torch.float32, "dphase")
+    nc = configs.shape[0]
+    g = out if out is not None else torch.empty(param_count(m), dtype=torch.float64, device=params.device)
+    buf, nb = _ws(ws, m, None, nc)
+    _check(lib().rnn_logpsi_grad(ctypes.byref(m), _ptr(params), nc, _ptr(configs), _ptr(dlogp), _ptr(dphase),
+                                 _ptr(g), _ptr(buf), nb, _stream()))
+    return g
+
+
+class LogPsi(torch.autograd.Function):
+    """(log P, phi) of given configurations as a differentiable function of the
+    flat parameters: forward rnn_logpsi, backward rnn_logpsi_grad (the
+    hand-written reverse sweep)."""
+
+    @staticmethod
+    def forward(ctx, params, configs, m):
+        lp, ph = rnn_logpsi(m, params, configs)
+        ctx.save_for_backward(params, configs)
+        ctx.m = m
+        return lp, ph
+
+    @staticmethod
+    def backward(ctx, glp, gph):
+        params, configs = ctx.saved_tensors
+        if glp is None:
+            glp = torch.zeros(configs.shape[0], dtype=torch.float32, device=params.device)
+        gph = None if (gph is None or not ctx.m.is_complex) else gph.float().contiguous()
+        g = rnn_logpsi_grad(ctx.m, params, configs, glp.float().contiguous(), gph)
+        return g.to(params.dtype), None, None
+
+
+def logpsi(m, params, configs):
+    """Differentiable (log P [nc], phase [nc]); see LogPsi."""
+    return LogPsi.apply(params, configs, m)
 
 
 def local_energy(m, params, H, configs, ws=None, out=None):

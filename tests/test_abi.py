@@ -31,8 +31,9 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = declared()
-    assert set(names) == {"vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "local_energy",
-                          "vmc_grad", "vmc_step", "grow_hidden", "vmc_chain_timing", "vmc_chain_time", "vmc_status_str"}
+    assert set(names) == {"vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "rnn_logpsi_grad",
+                          "local_energy", "vmc_grad", "vmc_step", "grow_hidden", "vmc_chain_timing",
+                          "vmc_chain_time", "vmc_status_str"}
     L = ctypes.CDLL(LIB)
     for n in names:
         assert hasattr(L, n), n
@@ -84,6 +85,8 @@ def test_argument_errors_before_launch(lib):
     assert L.rnn_sample(ctypes.byref(m), fake, 100, 0, 0, None, None, fake, None, ws, need, None) == -1
     assert L.rnn_logpsi(ctypes.byref(m), None, 100, fake, fake, None, ws, need, None) == -1
     assert L.vmc_grad(ctypes.byref(m), fake, 100, fake, None, None, fake, None, ws, need, None) == -1
+    assert L.rnn_logpsi_grad(ctypes.byref(m), fake, 100, fake, None, None, fake, ws, need, None) == -1
+    assert L.rnn_logpsi_grad(ctypes.byref(m), fake, 100, fake, fake, None, fake, ws, need - 1, None) == -3
     assert L.local_energy(ctypes.byref(m), fake, None, 100, fake, fake, ws, need, None) == -1
     badH = lib.Ham(5, 0, 1.0, 1.0)
     assert L.local_energy(ctypes.byref(m), fake, ctypes.byref(badH), 100, fake, fake, ws, need, None) == -1

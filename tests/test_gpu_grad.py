@@ -128,3 +128,38 @@ def test_grad_directional_finite_differences(case):
 
         fd = (L(p + eps * v) - L(p - eps * v)) / (2 * eps)
         assert abs(fd - g @ v) <= 2e-3 * max(abs(g @ v), 1e-2 * np.linalg.norm(g))
+
+
+@pytest.mark.parametrize("case", [GRAD_CASES[1], GRAD_CASES[2], GRAD_CASES[5], GRAD_CASES[7]], ids=_ids)
+@pytest.mark.parametrize("bf16", [False, True], ids=["fp32", "bf16"])
+def test_logpsi_autograd(case, bf16):
+    """torch.autograd through LogPsi (forward rnn_logpsi, backward the reverse
+    sweep via rnn_logpsi_grad) against the oracle's gradient of
+    L = sum_s a_s logP_s + b_s phi_s with the same a, b."""
+    torch = torch_gpu()
+    from oracle import oracle as O
+    from paper_2507_18700_amd import vmcrnn as V
+    dims, Lx, Ly, dh, cplx, glu = case
+    spec, gm, _ = lib_and_oracle(dims, Lx, Ly, dh, cplx, glu, bf16)
+    _, _, om = lib_and_oracle(dims, Lx, Ly, dh, cplx, glu, False)
+    p = synth.xavier_params(spec, 61, bias_scale=0.2)
+    ns = 83
+    cfg = synth.configs(ns, spec.N, 62)
+    rng = np.random.default_rng(63)
+    a = rng.standard_normal(ns).astype(np.float32)
+    b = rng.standard_normal(ns).astype(np.float32)
+    pt = torch.from_numpy(p).cuda().requires_grad_(True)
+    cd = torch.from_numpy(cfg).cuda()
+    lp, ph = V.logpsi(gm, pt, cd)
+    loss = (lp * torch.from_numpy(a).cuda()).sum() + (ph * torch.from_numpy(b).cuda()).sum()
+    (g,) = torch.autograd.grad(loss, pt)
+    torch.cuda.synchronize()
+    assert g.dtype == torch.float32 and g.shape == pt.shape
+    # the forward values are those of rnn_logpsi
+    lp2, ph2 = V.rnn_logpsi(gm, pt.detach(), cd)
+    assert torch.equal(lp.detach(), lp2) and torch.equal(ph.detach(), ph2)
+    ref = O.surrogate_grad(om, p.astype(np.float64), cfg, a.astype(np.float64),
+                           b.astype(np.float64) if cplx else None)
+    tol = 1e-2 if bf16 else 1e-5
+    err = rel_l2(g.double().cpu().numpy(), ref)
+    assert err < tol, "relative l2 error %.3g" % err

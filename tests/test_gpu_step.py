@@ -47,3 +47,49 @@ def test_step_equals_separate_calls(case):
         assert rel_l2(g.cpu().numpy(), rg) < 1e-5
         uni = O.philox_uniforms(5, 3, ns, spec.N)
         check_samples(O, om, p64, c, uni, spec.Lx, spec.Ly, 1e-5)
+
+
+@pytest.mark.parametrize("case", [STEP_CASES[1], STEP_CASES[3]], ids=lambda c: "%dD_%dx%d_dh%d_c%d_g%d_%s_bf%d" % c)
+def test_step_graph_replay(case):
+    """A vmc_step captured in a HIP graph (no allocation, no host sync and no
+    memset inside the call) replays to the eager result, bit for bit, on every
+    replay, with eager work and synchronisations between the replays."""
+    torch = torch_gpu()
+    from paper_2507_18700_amd import vmcrnn as V
+    dims, Lx, Ly, dh, cplx, glu, kind, bf16 = case
+    spec, gm, _ = lib_and_oracle(dims, Lx, Ly, dh, cplx, glu, bf16)
+    p = torch.from_numpy(synth.xavier_params(spec, 71, bias_scale=0.2)).cuda()
+    H = V.ham(V.VMC_HEISENBERG, 1.0, 0.0, True) if kind == "heis" else V.ham(V.VMC_TFIM, 1.0, 2.0)
+    ns = 150
+    ws = V.Workspace()
+    ws.get(V.workspace_size(gm, H, ns))
+
+    def outs():
+        return (torch.empty((ns, spec.N), dtype=torch.uint8, device="cuda"),
+                torch.empty(ns, dtype=torch.float32, device="cuda"),
+                torch.empty(ns, dtype=torch.float32, device="cuda"),
+                torch.empty((ns, 2), dtype=torch.float64, device="cuda"),
+                torch.empty(V.param_count(gm), dtype=torch.float64, device="cuda"),
+                torch.empty(4, dtype=torch.float64, device="cuda"))
+
+    ref = V.vmc_step(gm, p, H, ns, seed=9, counter=4, ws=ws, out=outs())
+    torch.cuda.synchronize()
+    got = outs()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        V.vmc_step(gm, p, H, ns, seed=9, counter=4, ws=ws, out=got)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        V.vmc_step(gm, p, H, ns, seed=9, counter=4, ws=ws, out=got)
+    for rep in range(3):
+        for t in got:
+            t.zero_()
+        ws.buf.fill_(7)  # the workspace holds no state between calls
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(ref, got):
+            assert torch.equal(a, b), "replay %d" % rep
