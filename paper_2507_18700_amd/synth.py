@@ -117,3 +117,13 @@ def eloc_values(ns, seed, complex_=False, scale=1.0):
     if complex_:
         e[:, 1] = scale * rng.standard_normal(ns)
     return e
+
+
+def uneven_chains(count, seed, n_lo=32, n_hi=128, h_lo=0.5, h_hi=1.5):
+    """A batch of independent 1D TFIM problems of uneven length: chain lengths
+    uniform in {n_lo..n_hi} and transverse fields uniform in [h_lo, h_hi]
+    (numpy PCG64 stream `seed`); returns [(N_c, h_c)]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = rng.integers(n_lo, n_hi + 1, size=count)
+    hs = rng.uniform(h_lo, h_hi, size=count)
+    return [(int(n), float(h)) for n, h in zip(ns, hs)]

@@ -308,3 +308,66 @@ def chain_time():
     n = ctypes.c_int64(0)
     _check(lib().vmc_chain_time(ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+class StepBatch:
+    """One VMC step of several independent problems (uneven chains, other
+    couplings) replayed as one HIP graph.  Each problem is a dict with keys
+    model, params, ham, ns and optionally seed, counter; each gets its own
+    workspace and outputs (`outputs[i]` = (configs, logp, phase, eloc, grad,
+    stats) of problem i).  The problems are spread over `streams` side
+    streams, longest first (work ~ ns * N^2) onto the least loaded stream,
+    so that their launches overlap on the GPU; capture() records everything
+    once, replay() runs the whole batch."""
+
+    def __init__(self, problems, streams=4):
+        self.problems = problems
+        self.outputs = []
+        self.workspaces = []
+        for pb in problems:
+            m, ns, dev = pb["model"], pb["ns"], pb["params"].device
+            ws = Workspace(dev)
+            ws.get(workspace_size(m, pb["ham"], ns))
+            self.workspaces.append(ws)
+            self.outputs.append((torch.empty((ns, m.N), dtype=torch.uint8, device=dev),
+                                 torch.empty(ns, dtype=torch.float32, device=dev),
+                                 torch.empty(ns, dtype=torch.float32, device=dev),
+                                 torch.empty((ns, 2), dtype=torch.float64, device=dev),
+                                 torch.empty(param_count(m), dtype=torch.float64, device=dev),
+                                 torch.empty(4, dtype=torch.float64, device=dev)))
+        nstream = max(1, min(streams, len(problems)))
+        self.streams = [torch.cuda.Stream() for _ in range(nstream)]
+        load = [0.0] * nstream
+        self.assign = [[] for _ in range(nstream)]
+        order = sorted(range(len(problems)), key=lambda i: -problems[i]["ns"] * problems[i]["model"].N ** 2)
+        for i in order:
+            k = min(range(nstream), key=lambda j: load[j])
+            self.assign[k].append(i)
+            load[k] += problems[i]["ns"] * problems[i]["model"].N ** 2
+        self.graph = None
+
+    def _issue(self):
+        main = torch.cuda.current_stream()
+        for s, idx in zip(self.streams, self.assign):
+            s.wait_stream(main)
+            with torch.cuda.stream(s):
+                for i in idx:
+                    pb = self.problems[i]
+                    vmc_step(pb["model"], pb["params"], pb["ham"], pb["ns"], seed=pb.get("seed", 0),
+                             counter=pb.get("counter", 0), ws=self.workspaces[i], out=self.outputs[i])
+        for s in self.streams:
+            main.wait_stream(s)
+
+    def run_eager(self):
+        self._issue()
+
+    def capture(self):
+        self._issue()  # warm-up outside the graph (launch attributes, library load)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._issue()
+        return self
+
+    def replay(self):
+        self.graph.replay()
