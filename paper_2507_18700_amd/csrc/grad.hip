@@ -78,7 +78,9 @@ struct DwArgs {
     int MD, K, Mp, Kp;    // delta rows, hidden input columns, padded output dims
     const void *hT, *gT;  // transposed hidden states / GLU outputs [N][DH][nsp]
     const void *xT;       // transposed extra inputs [N][5][nsp]: 1, onehot_hz(2), onehot_vt(2)
-    float *part;          // [N][Mp][Kp]
+    float *part;          // [N*nchunk][Mp][Kp]
+    int nchunk;           // sample chunks per position (split of the contraction)
+    int64_t chunk;        // samples per chunk (multiple of 32)
 };
 
 // Source row of input column k of segment seg at position q: a hidden state
@@ -121,17 +123,20 @@ __global__ void build_extras(Dims d, int64_t ns, int64_t nsp, const uint8_t *cfg
     }
 }
 
-// dW[m][k] at one position q (grid z): sum over samples of A[q][m][s] X[q][k][s]
-// on MFMA, operands read as 16-byte fragments straight from memory.  128x128
-// output tile, 4 waves as 2x2 of 64x64.
+// dW[m][k] at one position q, over one chunk of samples (grid z = q * nchunk
+// + chunk): sum over samples of A[q][m][s] X[q][k][s] on MFMA, operands read
+// as 16-byte fragments straight from memory, the next k-step's fragments in
+// flight while the current one's MFMAs run.  128x128 output tile, 4 waves as
+// 2x2 of 64x64.
 template <class P>
 __global__ __launch_bounds__(256) void dw_mfma(DwArgs a) {
     typedef typename P::store_t T;
     constexpr int VEC = P::VEC, KS = P::KSTEP;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, lq = lane >> 4;
     const int m0 = blockIdx.x * DW_TILE + (w >> 1) * 64, k0 = blockIdx.y * DW_TILE + (w & 1) * 64;
-    const int q = blockIdx.z;
+    const int q = blockIdx.z / a.nchunk, cidx = blockIdx.z - q * a.nchunk;
     const int64_t nsp = a.nsp;
+    const int64_t sbeg = (int64_t)cidx * a.chunk, send = min(nsp, sbeg + a.chunk);
     const T *A = (const T *)a.A + (int64_t)q * a.MD * nsp;
     const T *X = (const T *)(a.seg == 2 && a.d.glu ? a.gT : a.hT);
     const T *XE = (const T *)a.xT;
@@ -160,13 +165,14 @@ __global__ __launch_bounds__(256) void dw_mfma(DwArgs a) {
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    for (int64_t s0 = 0; s0 < nsp; s0 += KS) {
-        uint4 af[4], bf[4];
+    auto load = [&](int64_t s0, uint4 *af, uint4 *bf) {
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            af[i] = mon[i] ? *(const uint4 *)(ap[i] + s0) : make_uint4(0, 0, 0, 0);
-            bf[i] = bp[i] ? *(const uint4 *)(bp[i] + s0) : make_uint4(0, 0, 0, 0);
+            af[i] = (mon[i] && s0 < send) ? *(const uint4 *)(ap[i] + s0) : make_uint4(0, 0, 0, 0);
+            bf[i] = (bp[i] && s0 < send) ? *(const uint4 *)(bp[i] + s0) : make_uint4(0, 0, 0, 0);
         }
+    };
+    auto step = [&](const uint4 *af, const uint4 *bf) {
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             if (!mon[i]) continue;
@@ -174,8 +180,16 @@ __global__ __launch_bounds__(256) void dw_mfma(DwArgs a) {
             for (int j = 0; j < 4; j++)
                 if (kon[j]) P::mma(acc[i][j], af[i], bf[j]);
         }
+    };
+    uint4 fa[2][4], fb[2][4];
+    load(sbeg, fa[0], fb[0]);
+    for (int64_t s0 = sbeg; s0 < send; s0 += 2 * KS) {
+        load(s0 + KS, fa[1], fb[1]);
+        step(fa[0], fb[0]);
+        load(s0 + 2 * KS, fa[0], fb[0]);
+        step(fa[1], fb[1]);
     }
-    float *out = a.part + (int64_t)q * a.Mp * a.Kp;
+    float *out = a.part + (int64_t)blockIdx.z * a.Mp * a.Kp;
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -245,18 +259,33 @@ __device__ inline int64_t dw_param(const Dims &d, int seg, int m, int k) {
     return -1;
 }
 
-// FP64 sum of the per-position partials (fixed order), scattered into the
-// flat gradient.
-__global__ void dw_reduce(Dims d, int seg, const float *part, int Q, int Mp, int Kp, int K, int MD, double *grad) {
-    const int W = K + 5;
-    const int64_t n = (int64_t)MD * W;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int m = (int)(e / W), k = (int)(e % W);
+// FP64 sum of the per-position (and per-chunk) partials, scattered into the
+// flat gradient.  A work-group reduces 32 consecutive columns of one output
+// row: 8 groups of 32 threads take every 8th partial (4 loads in flight per
+// thread), then the 8 group sums are added in a fixed order.
+__global__ __launch_bounds__(256) void dw_reduce(Dims d, int seg, const float *part, int Q, int Mp, int Kp, int K,
+                                                 int MD, double *grad) {
+    __shared__ double sg[8][32];
+    const int W = K + 5, nkb = (W + 31) / 32;
+    const int m = blockIdx.x / nkb, k = (blockIdx.x % nkb) * 32 + (threadIdx.x & 31), g = threadIdx.x >> 5;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (m < MD && k < W) {
+        const float *src = part + (int64_t)m * Kp + k;
+        const int64_t stride = (int64_t)Mp * Kp;
+        int q = g;
+        for (; q + 24 < Q; q += 32) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) acc[u] += (double)src[(int64_t)(q + 8 * u) * stride];
+        }
+        for (int u = 0; q < Q; q += 8, u++) acc[u & 3] += (double)src[(int64_t)q * stride];
+    }
+    sg[g][threadIdx.x & 31] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __syncthreads();
+    if (g == 0 && m < MD && k < W) {
+        double t = 0.0;
+        for (int i = 0; i < 8; i++) t += sg[i][threadIdx.x];
         const int64_t idx = dw_param(d, seg, m, k);
-        if (idx < 0) continue;
-        double s = 0.0;
-        for (int q = 0; q < Q; q++) s += (double)part[((int64_t)q * Mp + m) * Kp + k];
-        grad[idx] = s;
+        if (idx >= 0) grad[idx] = t;
     }
 }
 
@@ -290,18 +319,31 @@ static SegDims seg_dims(const Dims &d, int seg) {
 
 int64_t grad_nsp(int64_t ns) { return (ns + 31) / 32 * 32; }
 
+// Sample chunks per position of the weight-gradient contraction: enough
+// work-groups to fill the chip several times over, chunks of >= 512 samples.
+static int dw_chunks(const Dims &d, const SegDims &s, int64_t nsp) {
+    const int64_t tiles = (int64_t)(s.Mp / DW_TILE) * (s.Kp / DW_TILE) * d.N;
+    int64_t c = (4096 + tiles - 1) / tiles;
+    const int64_t cmax = nsp / 512 > 1 ? nsp / 512 : 1;
+    if (c > cmax) c = cmax;
+    if (c > 16) c = 16;
+    return (int)(c < 1 ? 1 : c);
+}
+
 void grad_sizes(const Dims &d, int64_t ns, size_t *part_floats) {
+    const int64_t nsp = grad_nsp(ns);
     size_t mx = 0;
     for (int seg = 0; seg < 3; seg++) {
         SegDims s = seg_dims(d, seg);
-        mx = (size_t)s.Mp * s.Kp > mx ? (size_t)s.Mp * s.Kp : mx;
+        const size_t n = (size_t)dw_chunks(d, s, nsp) * s.Mp * s.Kp;
+        mx = n > mx ? n : mx;
     }
     *part_floats = (size_t)d.N * mx;
 }
 
 template <class P>
 static void launch_dw_p(const DwArgs &a, const SegDims &sd, hipStream_t st) {
-    dim3 grd(sd.Mp / DW_TILE, sd.Kp / DW_TILE, a.d.N);
+    dim3 grd(sd.Mp / DW_TILE, sd.Kp / DW_TILE, a.d.N * a.nchunk);
     hipLaunchKernelGGL(dw_mfma<P>, grd, dim3(256), 0, st, a);
 }
 
@@ -340,12 +382,13 @@ hipError_t launch_grad(const GradBufs &b, hipStream_t st) {
         a.gT = b.gT;
         a.xT = b.xT;
         a.part = b.part;
+        a.nchunk = dw_chunks(d, sd, a.nsp);
+        a.chunk = ((a.nsp + a.nchunk - 1) / a.nchunk + 31) / 32 * 32;
         if (d.prec == VMC_BF16) launch_dw_p<BF16>(a, sd, st);
         else launch_dw_p<F32>(a, sd, st);
-        const int64_t n = (int64_t)sd.MD * (sd.K + 5);
-        int rg = (int)((n + 255) / 256);
-        hipLaunchKernelGGL(dw_reduce, dim3(rg), dim3(256), 0, st, d, seg, b.part, d.N, sd.Mp, sd.Kp, sd.K, sd.MD,
-                           b.grad);
+        const int rg = sd.MD * ((sd.K + 5 + 31) / 32);
+        hipLaunchKernelGGL(dw_reduce, dim3(rg), dim3(256), 0, st, d, seg, b.part, d.N * a.nchunk, sd.Mp, sd.Kp, sd.K,
+                           sd.MD, b.grad);
     }
     return hipGetLastError();
 }
