@@ -166,6 +166,49 @@ vmc_status grow_hidden(const vmc_model *from, const float *p_from, int32_t new_d
                        double noise_std, float *p_to, const float *m_from, const float *v_from,
                        float *m_to, float *v_to, void *stream);
 
+/* Launch tuning.  Two launch choices per model shape (dims, Lx, Ly, d_h,
+ * precision, glu, is_complex) are kept in a process-wide table that every call
+ * above reads:
+ *  row_tile:          rows per work-group tile of the sampling and log psi
+ *                     launches (rnn_sample, rnn_logpsi, and the forward pass
+ *                     of local_energy, vmc_grad, rnn_logpsi_grad, vmc_step);
+ *                     one of vmc_row_tile_options(); 0 = built-in choice;
+ *  chain_wgs_per_cu:  persistent work-groups per compute unit of the
+ *                     suffix-chain launch of local_energy, 1..4; 0 = built-in (2).
+ * No choice changes any output bit: each row of a tile and each connected
+ * configuration is computed independently of the tile and of the work-group
+ * that runs it.  vmc_workspace_size() covers every choice, so a workspace
+ * stays valid when the table changes.  The table is guarded by a mutex; a
+ * change while another thread runs the same shape affects only its speed. */
+typedef struct {
+    int32_t row_tile;
+    int32_t chain_wgs_per_cu;
+} vmc_tuning;
+
+/* The row-tile heights this model shape can run with (count 1 or 2; the
+ * built-in one first).  opts must hold 2 entries. */
+vmc_status vmc_row_tile_options(const vmc_model *m, int32_t *opts, int32_t *count);
+
+/* Set the tuning of this model shape (t = NULL restores the built-in
+ * choices).  EINVAL for a row_tile not among the options or a
+ * chain_wgs_per_cu outside 0..4. */
+vmc_status vmc_set_tuning(const vmc_model *m, const vmc_tuning *t);
+
+/* The choices in effect for this model shape, resolved (no zeros). */
+vmc_status vmc_get_tuning(const vmc_model *m, vmc_tuning *t);
+
+/* Autotuner: times vmc_step (same arguments and outputs) under each
+ * candidate, coordinate by coordinate from the tuning in effect (the row-tile
+ * options, then chain_wgs_per_cu = 1..4), `reps` steps each, fastest step
+ * kept (HIP events on `stream`), stores the winner in the table and returns
+ * it in *best (may be NULL).  Blocks until done (it synchronises on its
+ * events).  The outputs are those of a final step under the chosen tuning,
+ * the same bits as one vmc_step.  reps in 1..100. */
+vmc_status vmc_autotune_step(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns,
+                             uint64_t seed, uint64_t counter, const float *uniforms, uint8_t *configs,
+                             float *logp, float *phase, double *eloc, double *grad, double *stats,
+                             void *ws, size_t ws_bytes, void *stream, int32_t reps, vmc_tuning *best);
+
 /* Opt-in timing of the dominant launch, the batched suffix-chain kernel of
  * local_energy.  vmc_chain_timing(1) creates (once) a pool of HIP events,
  * resets the record and makes every following local_energy call record one

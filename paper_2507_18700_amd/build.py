@@ -34,7 +34,9 @@ def hipcc():
 
 
 def _flags(csrc):
-    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+    # -ffp-contract=on: a multiply-add is fused only where it is written as one
+    # expression, so every instantiation of a kernel template rounds alike
+    return ["--offload-arch=" + ARCH, "-O3", "-ffp-contract=on", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
             "-Wno-unused-variable", "-Wno-unused-but-set-variable", "-I" + os.path.join(ROOT, "include"),
             "-I" + csrc, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

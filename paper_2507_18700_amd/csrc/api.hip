@@ -2,6 +2,10 @@
 // workspace layout and the launch sequence of each call.
 #include <string.h>
 
+#include <array>
+#include <map>
+#include <mutex>
+
 #include "kernels.h"
 
 namespace vmc {
@@ -19,6 +23,8 @@ hipError_t launch_assemble(const vmc_ham &H, int Lx, int Ly, int64_t ns, const u
 int engine_kpx(const Dims &d);
 size_t engine_lds(const Dims &d);
 int forward_tile_rows(const Dims &d);
+int chain_tile_rows(const Dims &d);
+int row_tile_options(const Dims &d, int out[2]);
 int backward_tile_rows(int DH);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
 hipError_t launch_grad(const GradBufs &b, hipStream_t st);
@@ -49,6 +55,26 @@ static int padded_dh(int d) {
     return -1;
 }
 
+// ------------------------------------------------------------ tuning table
+// Launch choices per model shape, process-wide.  Every choice gives the same
+// result bits (rows are computed independently of their tile and of the
+// work-group that runs them), so the table only changes speed.
+static const int kChainWpcDefault = 2, kChainWpcMax = 4;
+typedef std::array<int, 7> ShapeKey;
+static std::mutex g_tune_mu;
+static std::map<ShapeKey, vmc_tuning> g_tune;
+
+static ShapeKey shape_key(const vmc_model *m) {
+    return ShapeKey{m->dims, m->Lx, m->dims == 2 ? m->Ly : 1, m->d_h, m->precision, m->glu, m->is_complex};
+}
+
+static vmc_tuning lookup_tuning(const vmc_model *m) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(shape_key(m));
+    if (it == g_tune.end()) return vmc_tuning{0, 0};
+    return it->second;
+}
+
 static Dims make_dims(const vmc_model *m) {
     Dims d;
     d.dims = m->dims;
@@ -63,6 +89,15 @@ static Dims make_dims(const vmc_model *m) {
     d.cplx = m->is_complex;
     d.glu = m->glu;
     d.prec = m->precision;
+    d.row_alt = 0;
+    d.chain_wpc = kChainWpcDefault;
+    const vmc_tuning t = lookup_tuning(m);
+    if (t.row_tile > 0) {
+        int opt[2];
+        const int n = row_tile_options(d, opt);
+        d.row_alt = n > 1 && t.row_tile == opt[1];
+    }
+    if (t.chain_wgs_per_cu > 0) d.chain_wpc = t.chain_wgs_per_cu;
     return d;
 }
 
@@ -126,13 +161,25 @@ static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
     w.tile_start = put((size_t)(d.N + 1) * 4);
     w.tile_counter = put(4);
     w.list = put((H && H->kind == VMC_HEISENBERG) ? (size_t)ns * nb * 4 : 4);
-    w.fwd_grid = (int)((ns + MT - 1) / MT);
-    w.chain_grid = 2 * device_cus();
-    const int g = w.fwd_grid > w.chain_grid ? w.fwd_grid : w.chain_grid;
-    w.colbuf = put(d.dims == 2 ? (size_t)g * d.Lx * MT * d.DH * es : 16);
+    // the row launches cover every column of the transposed activation
+    // arrays (nsp >= ns samples), so that the rows past ns hold zeros
+    const int64_t nsp = grad_nsp(ns);
+    w.fwd_grid = (int)((nsp + MT - 1) / MT);
+    w.chain_grid = d.chain_wpc * device_cus();
+    // the column buffer holds one tile-row block per work-group of the
+    // largest launch any tuning can make, so a workspace sized once stays
+    // valid when the tuning changes
+    int opt[2];
+    const int nopt = row_tile_options(d, opt);
+    size_t rows = (size_t)kChainWpcMax * device_cus() * chain_tile_rows(d);
+    for (int i = 0; i < nopt; i++) {
+        const size_t f = (size_t)((nsp + opt[i] - 1) / opt[i]) * opt[i];
+        rows = f > rows ? f : rows;
+    }
+    w.colbuf = put(d.dims == 2 ? rows * d.Lx * d.DH * es : 16);
     // backward
     const int nd_cell = d.dims == 1 ? 4 * d.DH : 3 * d.DH;
-    w.nsp = grad_nsp(ns);
+    w.nsp = nsp;
     w.act = put((size_t)d.N * act_feats(d.dims) * d.DH * w.nsp * 4);
     w.lgT = put((size_t)d.N * 4 * w.nsp * 4);
     w.hT = put((size_t)d.N * d.DH * w.nsp * es);
@@ -165,7 +212,11 @@ static vmc_status check_common(const vmc_model *m, const float *params, int64_t 
     if (padded_dh(m->d_h) < 0) return VMC_EUNSUPPORTED;
     if (n >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
     Dims d = make_dims(m);
-    if ((int64_t)forward_tile_rows(d) * d.N > 32768) return VMC_EUNSUPPORTED;
+    int opt[2];
+    const int nopt = row_tile_options(d, opt);
+    for (int i = 0; i < nopt; i++)
+        if ((int64_t)opt[i] * d.N > 32768) return VMC_EUNSUPPORTED;
+    if ((int64_t)chain_tile_rows(d) * d.N > 32768) return VMC_EUNSUPPORTED;
     if (engine_lds(d) > kMaxLds) return VMC_EUNSUPPORTED;
     if (H && H->kind == VMC_HEISENBERG && n * bond_count(d.Lx, d.Ly) >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
     WsMap w = ws_map(d, H, n);
@@ -275,7 +326,6 @@ vmc_status rnn_logpsi(const vmc_model *m, const float *params, int64_t nc, const
 // conditionals, prefix sums) holds the configurations.
 static vmc_status eloc_from_cache(const Dims &d, const WsMap &w, void *ws, const vmc_ham *H, int64_t ns,
                                   const uint8_t *configs, double *eloc, hipStream_t st) {
-    const int MT = forward_tile_rows(d);
     FwdArgs a = base_args(d, ws, w, ns);
     a.cfg_in = configs;
     a.hcache = at<float>(ws, w.hcache);
@@ -283,7 +333,8 @@ static vmc_status eloc_from_cache(const Dims &d, const WsMap &w, void *ws, const
     a.phc = at<float>(ws, w.phc);
     a.pre = at<double2>(ws, w.pre);
     hipError_t e = launch_sched(H->kind, d.Lx, d.Ly, ns, configs, at<int>(ws, w.cnt), at<int>(ws, w.list_off),
-                                at<int>(ws, w.list), at<int>(ws, w.tile_start), at<int>(ws, w.tile_counter), MT, st);
+                                at<int>(ws, w.list), at<int>(ws, w.tile_start), at<int>(ws, w.tile_counter),
+                                chain_tile_rows(d), st);
     if (e != hipSuccess) return VMC_EDEVICE;
     a.ham_kind = H->kind;
     a.nbond = bond_count(d.Lx, d.Ly);
@@ -496,6 +547,121 @@ vmc_status vmc_chain_time(double *ms_total, int64_t *launches) {
     *ms_total = tot;
     *launches = g_timing.n;
     return VMC_OK;
+}
+
+vmc_status vmc_row_tile_options(const vmc_model *m, int32_t *opts, int32_t *count) {
+    if (!valid_model(m) || !opts || !count) return VMC_EINVAL;
+    if (padded_dh(m->d_h) < 0) return VMC_EUNSUPPORTED;
+    Dims d = make_dims(m);
+    int o[2];
+    const int n = row_tile_options(d, o);
+    for (int i = 0; i < n; i++) opts[i] = o[i];
+    *count = n;
+    return VMC_OK;
+}
+
+vmc_status vmc_set_tuning(const vmc_model *m, const vmc_tuning *t) {
+    if (!valid_model(m)) return VMC_EINVAL;
+    if (padded_dh(m->d_h) < 0) return VMC_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!t) {
+        g_tune.erase(shape_key(m));
+        return VMC_OK;
+    }
+    if (t->chain_wgs_per_cu < 0 || t->chain_wgs_per_cu > kChainWpcMax) return VMC_EINVAL;
+    if (t->row_tile != 0) {
+        Dims d = {};
+        d.dims = m->dims;
+        d.DH = padded_dh(m->d_h);
+        d.prec = m->precision;
+        int o[2];
+        const int n = row_tile_options(d, o);
+        if (t->row_tile != o[0] && (n < 2 || t->row_tile != o[1])) return VMC_EINVAL;
+    }
+    g_tune[shape_key(m)] = *t;
+    return VMC_OK;
+}
+
+vmc_status vmc_get_tuning(const vmc_model *m, vmc_tuning *t) {
+    if (!valid_model(m) || !t) return VMC_EINVAL;
+    if (padded_dh(m->d_h) < 0) return VMC_EUNSUPPORTED;
+    Dims d = make_dims(m);
+    t->row_tile = forward_tile_rows(d);
+    t->chain_wgs_per_cu = d.chain_wpc;
+    return VMC_OK;
+}
+
+vmc_status vmc_autotune_step(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns, uint64_t seed,
+                             uint64_t counter, const float *uniforms, uint8_t *configs, float *logp, float *phase,
+                             double *eloc, double *grad, double *stats, void *ws, size_t ws_bytes, void *stream,
+                             int32_t reps, vmc_tuning *best) {
+    if (reps < 1 || reps > 100) return VMC_EINVAL;
+    if (!H || (H->kind != VMC_TFIM && H->kind != VMC_HEISENBERG)) return VMC_EINVAL;
+    vmc_status s = check_common(m, params, ns, ws, ws_bytes, H, NULL);
+    if (s != VMC_OK) return s;
+    if (!configs || !logp || !eloc || !grad) return VMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t ev[2];
+    if (hipEventCreate(&ev[0]) != hipSuccess) return VMC_EDEVICE;
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        hipEventDestroy(ev[0]);
+        return VMC_EDEVICE;
+    }
+    // fastest of `reps` steps under tuning t
+    auto timed = [&](const vmc_tuning &t, float *ms) -> vmc_status {
+        vmc_status r = vmc_set_tuning(m, &t);
+        if (r != VMC_OK) return r;
+        float bestms = 1e30f;
+        for (int i = 0; i < reps; i++) {
+            if (hipEventRecord(ev[0], st) != hipSuccess) return VMC_EDEVICE;
+            r = vmc_step(m, params, H, ns, seed, counter, uniforms, configs, logp, phase, eloc, grad, stats, ws,
+                         ws_bytes, stream);
+            if (r != VMC_OK) return r;
+            float t_ms = 0.f;
+            if (hipEventRecord(ev[1], st) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                hipEventElapsedTime(&t_ms, ev[0], ev[1]) != hipSuccess)
+                return VMC_EDEVICE;
+            bestms = t_ms < bestms ? t_ms : bestms;
+        }
+        *ms = bestms;
+        return VMC_OK;
+    };
+    // coordinate search from the tuning in effect: the row tile, then the
+    // persistent work-groups per compute unit of the chain launch
+    vmc_tuning cur;
+    s = vmc_get_tuning(m, &cur);
+    float cur_ms = 0.f;
+    if (s == VMC_OK) s = timed(cur, &cur_ms);
+    int32_t opts[2], nopt = 0;
+    if (s == VMC_OK) s = vmc_row_tile_options(m, opts, &nopt);
+    for (int i = 0; s == VMC_OK && i < nopt; i++) {
+        if (opts[i] == cur.row_tile) continue;
+        vmc_tuning t = cur;
+        t.row_tile = opts[i];
+        float ms = 0.f;
+        s = timed(t, &ms);
+        if (s == VMC_OK && ms < cur_ms) {
+            cur = t;
+            cur_ms = ms;
+        }
+    }
+    for (int wpc = 1; s == VMC_OK && wpc <= kChainWpcMax; wpc++) {
+        if (wpc == cur.chain_wgs_per_cu) continue;
+        vmc_tuning t = cur;
+        t.chain_wgs_per_cu = wpc;
+        float ms = 0.f;
+        s = timed(t, &ms);
+        if (s == VMC_OK && ms < cur_ms) {
+            cur = t;
+            cur_ms = ms;
+        }
+    }
+    // the outputs left behind are those of one step under the chosen tuning
+    if (s == VMC_OK) s = timed(cur, &cur_ms);
+    if (s == VMC_OK && best) *best = cur;
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    return s;
 }
 
 const char *vmc_status_str(vmc_status s) {

@@ -133,6 +133,9 @@ enum {
 
 struct Dims {
     int dims, Lx, Ly, N, dh, DH, K, KP, cplx, glu, prec;
+    // launch choices from the tuning table (host side): the alternative row
+    // tile, persistent work-groups per compute unit of the suffix-chain launch
+    int row_alt, chain_wpc;
 };
 
 __host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }

@@ -18,7 +18,26 @@ hipError_t launch_forward(const FwdArgs &a, int mode, int store_h, int store_lpc
                          : launch_engine_f32_2d(a, mode, store_h, store_lpc, store_act, grid, st);
 }
 
-int forward_tile_rows(const Dims &d) { return (d.DH >= 256 || (d.prec == VMC_FP32 && d.DH >= 128)) ? 32 : 64; }
+// Rows per tile of tile class tc (0, 1 or 2, see Eng) for this model.
+static int tile_rows(const Dims &d, int tc) {
+#define VMC_T(PP, D) (tc == 0 ? tile_rows_d<PP, D, 0>(d.DH) : tc == 1 ? tile_rows_d<PP, D, 1>(d.DH) : tile_rows_d<PP, D, 2>(d.DH))
+    if (d.prec == VMC_BF16) return d.dims == 1 ? VMC_T(BF16, 1) : VMC_T(BF16, 2);
+    return d.dims == 1 ? VMC_T(F32, 1) : VMC_T(F32, 2);
+#undef VMC_T
+}
+
+// Rows per tile of the sampling / log psi launches (the tuned choice) and of
+// the suffix-chain launch.
+int forward_tile_rows(const Dims &d) { return tile_rows(d, d.row_alt ? 2 : 0); }
+int chain_tile_rows(const Dims &d) { return tile_rows(d, 1); }
+
+// The row-tile heights a model can run with: the built-in one first, then
+// the alternative where one exists.  Returns the count (1 or 2).
+int row_tile_options(const Dims &d, int out[2]) {
+    out[0] = tile_rows(d, 0);
+    out[1] = tile_rows(d, 2);
+    return out[1] != out[0] ? 2 : 1;
+}
 
 // LDS of one engine workgroup (static tiles + the tile's configurations).
 size_t engine_lds(const Dims &d) {

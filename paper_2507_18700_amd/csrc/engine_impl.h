@@ -32,20 +32,34 @@
 // indicator tiles and triple-buffered head sums.  Sampling draws the spin of
 // q before the cell of q+1 can start and keeps three barriers per position.
 #pragma once
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.h"
 
 namespace vmc {
 
-template <class P, int DIMS, int DH, int NW>
+// Tile shape by tile class TC.  TC = 1: the suffix-chain launch (persistent).
+// TC = 0: one tile per work-group over the samples (sampling, log psi), made
+// shorter at bfloat16 d_h = 128 (48 rows) so that 10^4 samples occupy more
+// compute units.  TC = 2: the alternative row tile that the tuning table can
+// select (64 rows there, half the chain tile elsewhere); where it does not
+// exist (HAS_ALT false) TC = 2 has the TC = 0 shape and is never launched.
+// Every row of a tile is computed independently of the others, so the tile
+// choice does not change any result bit.
+template <class P, int DIMS, int DH, int NW, int TC = 0>
 struct Eng {
     static constexpr int WU = (DH / 16 < NW) ? DH / 16 : NW;  // waves along hidden units
     static constexpr int WR = NW / WU;                        // waves along rows
     static constexpr int UW = DH / WU;
     static constexpr int UB = UW / 16;
     // rows per tile (FP32 tiles at d_h >= 128 are halved to fit the LDS)
-    static constexpr int MT = (DH >= 256 || (P::VEC == 4 && DH >= 128)) ? 32 : 64;
+    static constexpr int MT_CHAIN = (DH >= 256 || (P::VEC == 4 && DH >= 128)) ? 32 : 64;
+    static constexpr bool BIG = P::VEC == 8 && DH == 128 && NW == 8;
+    static constexpr int MT_ROW = BIG ? 48 : MT_CHAIN;
+    static constexpr int MT_ALT = BIG ? 64 : MT_CHAIN / 2;
+    static constexpr bool HAS_ALT = MT_ALT != MT_ROW && MT_ALT % (16 * WR) == 0;
+    static constexpr int MT = TC == 1 ? MT_CHAIN : (TC == 2 && HAS_ALT) ? MT_ALT : MT_ROW;
     static constexpr int RW = MT / WR;
     static constexpr int RB = RW / 16;
     static constexpr int KS = P::KSTEP;
@@ -64,15 +78,15 @@ struct Eng {
         4 * ((size_t)NLOG * WU * MT * 4 + 2 * DH) + 8 * MT + 16 * MT + 16;
 };
 
-// Sum over the four 16-lane groups of a wave (lanes l, l^16, l^32, l^48);
-// every lane gets the sum, with the same bits in all four lanes.  Two
-// cross-row swaps (v_permlane16_swap, v_permlane32_swap) and two adds.
-__device__ inline float group4_sum(float v) {
-    const uint32_t b = __float_as_uint(v);
-    const auto x = __builtin_amdgcn_permlane16_swap(b, b, false, false);
+// Sums over the four 16-lane groups of two values at once: p ends up summed
+// in lanes 0-31 and q in lanes 32-63 (same bits within each half).  One
+// v_permlane32_swap exchanges the upper half of p with the lower half of q,
+// one v_permlane16_swap then pairs the remaining rows.
+__device__ inline float pair_sum4(float p, float q) {
+    const auto x = __builtin_amdgcn_permlane32_swap(__float_as_uint(p), __float_as_uint(q), false, false);
     const float s = __uint_as_float(x[0]) + __uint_as_float(x[1]);
     const uint32_t c = __float_as_uint(s);
-    const auto y = __builtin_amdgcn_permlane32_swap(c, c, false, false);
+    const auto y = __builtin_amdgcn_permlane16_swap(c, c, false, false);
     return __uint_as_float(y[0]) + __uint_as_float(y[1]);
 }
 
@@ -101,12 +115,12 @@ struct PosInfo {
     bool colw;  // h of this position is a later vertical input (kept in the column buffer)
 };
 
-template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF>
+template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF, int TC>
 __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int store_h_, int store_lpc_,
                                                       int store_act_) {
     // cache writes exist only in the STORE variant (the chain kernel has none)
     const int store_h = STORE && store_h_, store_lpc = STORE && store_lpc_, store_act = STORE && store_act_;
-    typedef Eng<P, DIMS, DH, NW> C;
+    typedef Eng<P, DIMS, DH, NW, TC> C;
     typedef typename P::store_t T;
     constexpr int MT = C::MT, RB = C::RB, UB = C::UB, KS = C::KS, VEC = P::VEC;
     constexpr int KHB = C::KHB, NKB = C::NKB, NKS = C::NKS, KPX = C::KPX;
@@ -157,6 +171,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             }
         }
     for (int e = tid; e < 2 * DH; e += NT) (&sHw[0][0])[e] = a.Hd[2 * DH + e];
+    for (int e = tid; e < C::NLOG * C::WU * MT * 4; e += NT) (&sLog[0][0][0][0])[e] = 0.f;
     const float hc0 = a.hc[0], hc1 = a.hc[1], hc2 = a.hc[2], hc3 = a.hc[3];
 
     // REGW: cell and GLU weight fragments in registers for the whole launch
@@ -207,14 +222,17 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 
     // Head outputs of one 16-row block: sum the lane partials over the four
     // lane groups of a row, then one lane group stores the wave's sums.
+    // the wave's partial logits of row r: the amplitude pair from lanes 0-15
+    // (logit 0) and 32-47 (logit 1), the phase pair likewise; the phase slots
+    // of a positive RNN stay at the zeros written at the start
     auto head_out = [&](int lb, int r, float p0, float p1, float p2, float p3) __attribute__((always_inline)) {
-        p0 = group4_sum(p0);
-        p1 = group4_sum(p1);
-        if (cplx) {
-            p2 = group4_sum(p2);
-            p3 = group4_sum(p3);
+        const float t01 = pair_sum4(p0, p1);
+        const float t23 = cplx ? pair_sum4(p2, p3) : 0.f;
+        if ((lq & 1) == 0) {
+            float *d = &sLog[lb][wu][r][lq >> 1];
+            d[0] = t01;
+            if (cplx) d[2] = t23;
         }
-        if (lq == 0) *(float4 *)&sLog[lb][wu][r][0] = make_float4(p0, p1, p2, p3);
     };
     // partial head sums of the lane's 4 units of one row
     auto head_part = [&](int ub, const float *g, float &p0, float &p1, float &p2, float &p3) __attribute__((always_inline)) {
@@ -411,13 +429,13 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                         const float cin = bin_[ud][i] + (xz == 0 ? win0[ud][i] : (xz == 1 ? win1[ud][i] : 0.f));
                         const float c = tanhf_(rr * g2 + cin);
                         float &hp = hreg[rb % (DIMS == 1 ? RB : 1)][ud][i];
-                        h = (1.0f - uu) * hp + uu * c;
+                        h = hp + uu * (c - hp);
                         hp = h;
                         s0 = uu; s1 = rr; s2 = g2; s3 = c;
                     } else {
                         const float c = tanhf_(g0);
                         const float uu = sigmoidf_(g1);
-                        h = uu * c + (1.0f - uu) * g2;
+                        h = g2 + uu * (c - g2);
                         s0 = c; s1 = uu; s2 = g2;
                     }
                     hq[i] = (STORE && s < 0) ? 0.f : h;
@@ -462,8 +480,8 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 float g[4], a1[4], a2[4];
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
-                    a1[i] = acc2[ub][i] + gb1[ub][i];
-                    a2[i] = acc2[UB + ub][i] + gb2[ub][i];
+                    a1[i] = acc2[ub][i];  // the biases entered as the accumulators' start
+                    a2[i] = acc2[UB + ub][i];
                     g[i] = a1[i] * sigmoidf_(a2[i]);
                 }
                 head_part(ub, g, p0, p1, p2, p3);
@@ -497,7 +515,10 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             if (REGW) {
                 auto gblock = [&](int rb, f32x4_t *acc2) __attribute__((always_inline)) {
 #pragma unroll
-                    for (int c = 0; c < 2 * UB; c++) acc2[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+                    for (int ub = 0; ub < UB; ub++) {
+                        acc2[ub] = f32x4_t{gb1[ub][0], gb1[ub][1], gb1[ub][2], gb1[ub][3]};
+                        acc2[UB + ub] = f32x4_t{gb2[ub][0], gb2[ub][1], gb2[ub][2], gb2[ub][3]};
+                    }
 #pragma unroll
                     for (int kq = 0; kq < NKG; kq++) {
                         const uint4 af = glu_frag(qg, rb, kq * KS);
@@ -551,7 +572,10 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 #pragma unroll
                     for (int rb = 0; rb < RB; rb++)
 #pragma unroll
-                        for (int c = 0; c < 2 * UB; c++) acc2[rb][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+                        for (int ub = 0; ub < UB; ub++) {
+                            acc2[rb][ub] = f32x4_t{gb1[ub][0], gb1[ub][1], gb1[ub][2], gb1[ub][3]};
+                            acc2[rb][UB + ub] = f32x4_t{gb2[ub][0], gb2[ub][1], gb2[ub][2], gb2[ub][3]};
+                        }
 #pragma unroll 2
                     for (int kk = 0; kk < KHB; kk += KS) {
                         uint4 af[RB];
@@ -753,26 +777,36 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 
 // ------------------------------------------------------------ launchers
 
-template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF>
+template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF, int TC>
 static hipError_t launch_engine_s(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
-    typedef Eng<P, DIMS, DH, NW> C;
+    typedef Eng<P, DIMS, DH, NW, TC> C;
     size_t dyn = ((size_t)C::MT * a.d.N + 15) / 16 * 16;
-    hipError_t e = hipFuncSetAttribute((const void *)rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF>,
+    hipError_t e = hipFuncSetAttribute((const void *)rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF, TC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF>), dim3(grid), dim3(NW * 64), dyn, st, a, mode,
+    hipLaunchKernelGGL((rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF, TC>), dim3(grid), dim3(NW * 64), dyn, st, a, mode,
                        sh, sl, sa);
     return hipGetLastError();
 }
 
-template <class P, int DIMS, int DH, int NW, int REGW>
-static hipError_t launch_engine_t(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
+// row launches of tile class TC (0 or 2)
+template <class P, int DIMS, int DH, int NW, int REGW, int TC>
+static hipError_t launch_engine_r(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
     const bool store = sh || sl || sa, tf = mode != MODE_SAMPLE;
     if (store)
-        return tf ? launch_engine_s<P, DIMS, DH, NW, REGW, 1, 1>(a, mode, sh, sl, sa, grid, st)
-                  : launch_engine_s<P, DIMS, DH, NW, REGW, 1, 0>(a, mode, sh, sl, sa, grid, st);
-    return tf ? launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1>(a, mode, sh, sl, sa, grid, st)
-              : launch_engine_s<P, DIMS, DH, NW, REGW, 0, 0>(a, mode, sh, sl, sa, grid, st);
+        return tf ? launch_engine_s<P, DIMS, DH, NW, REGW, 1, 1, TC>(a, mode, sh, sl, sa, grid, st)
+                  : launch_engine_s<P, DIMS, DH, NW, REGW, 1, 0, TC>(a, mode, sh, sl, sa, grid, st);
+    return tf ? launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, TC>(a, mode, sh, sl, sa, grid, st)
+              : launch_engine_s<P, DIMS, DH, NW, REGW, 0, 0, TC>(a, mode, sh, sl, sa, grid, st);
+}
+
+template <class P, int DIMS, int DH, int NW, int REGW>
+static hipError_t launch_engine_t(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
+    if (mode == MODE_CHAIN) return launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, 1>(a, mode, sh, sl, sa, grid, st);
+    if constexpr (Eng<P, DIMS, DH, NW, 2>::HAS_ALT) {
+        if (a.d.row_alt) return launch_engine_r<P, DIMS, DH, NW, REGW, 2>(a, mode, sh, sl, sa, grid, st);
+    }
+    return launch_engine_r<P, DIMS, DH, NW, REGW, 0>(a, mode, sh, sl, sa, grid, st);
 }
 
 // Variant per precision and width: bfloat16 up to d_h = 128 keeps the
@@ -798,9 +832,25 @@ static hipError_t launch_engine_d(const FwdArgs &a, int mode, int sh, int sl, in
     return hipErrorInvalidValue;
 }
 
+// rows per tile of tile class TC (2: 0 where no alternative exists)
+template <class P, int DIMS, int TC>
+static int tile_rows_d(int DH) {
+#define VMC_TR(DHV) Eng<P, DIMS, DHV, Pick<P, DHV>::NW, TC>::MT
+    switch (DH) {
+        case 16: return VMC_TR(16);
+        case 32: return VMC_TR(32);
+        case 64: return VMC_TR(64);
+        case 128: return VMC_TR(128);
+        case 256: return VMC_TR(256);
+    }
+#undef VMC_TR
+    return 64;
+}
+
 template <class P, int DIMS>
 static size_t engine_lds_d(int DH, int N) {
-#define VMC_LDS(DHV) Eng<P, DIMS, DHV, Pick<P, DHV>::NW>::LDS + (size_t)Eng<P, DIMS, DHV, 4>::MT * N
+#define VMC_LDS1(DHV, TC) (Eng<P, DIMS, DHV, Pick<P, DHV>::NW, TC>::LDS + (size_t)Eng<P, DIMS, DHV, Pick<P, DHV>::NW, TC>::MT * N)
+#define VMC_LDS(DHV) std::max(std::max(VMC_LDS1(DHV, 0), VMC_LDS1(DHV, 1)), VMC_LDS1(DHV, 2))
     switch (DH) {
         case 16: return VMC_LDS(16);
         case 32: return VMC_LDS(32);
@@ -809,6 +859,7 @@ static size_t engine_lds_d(int DH, int N) {
         case 256: return VMC_LDS(256);
     }
 #undef VMC_LDS
+#undef VMC_LDS1
     return (size_t)1 << 30;
 }
 

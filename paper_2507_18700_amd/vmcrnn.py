@@ -18,7 +18,8 @@ VMC_FP32, VMC_BF16 = 0, 1
 VMC_TFIM, VMC_HEISENBERG = 0, 1
 
 EXPORTS = ("vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "rnn_logpsi_grad", "local_energy",
-           "vmc_grad", "vmc_step", "grow_hidden", "vmc_chain_timing", "vmc_chain_time", "vmc_status_str")
+           "vmc_grad", "vmc_step", "grow_hidden", "vmc_row_tile_options", "vmc_set_tuning", "vmc_get_tuning",
+           "vmc_autotune_step", "vmc_chain_timing", "vmc_chain_time", "vmc_status_str")
 
 
 class VmcError(RuntimeError):
@@ -40,6 +41,10 @@ class Model(ctypes.Structure):
 class Ham(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("marshall", ctypes.c_int32), ("J", ctypes.c_double),
                 ("h", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("row_tile", ctypes.c_int32), ("chain_wgs_per_cu", ctypes.c_int32)]
 
 
 def model(dims=1, Lx=4, Ly=1, d_h=16, is_complex=False, glu=False, precision=VMC_FP32):
@@ -81,6 +86,15 @@ def lib():
         L.vmc_step.argtypes = [P(Model), vp, P(Ham), i64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.grow_hidden.restype = ctypes.c_int
         L.grow_hidden.argtypes = [P(Model), vp, ctypes.c_int32, u64, d, vp, vp, vp, vp, vp, vp]
+        L.vmc_row_tile_options.restype = ctypes.c_int
+        L.vmc_row_tile_options.argtypes = [P(Model), P(ctypes.c_int32), P(ctypes.c_int32)]
+        L.vmc_set_tuning.restype = ctypes.c_int
+        L.vmc_set_tuning.argtypes = [P(Model), P(Tuning)]
+        L.vmc_get_tuning.restype = ctypes.c_int
+        L.vmc_get_tuning.argtypes = [P(Model), P(Tuning)]
+        L.vmc_autotune_step.restype = ctypes.c_int
+        L.vmc_autotune_step.argtypes = [P(Model), vp, P(Ham), i64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp,
+                                        ctypes.c_int32, P(Tuning)]
         L.vmc_chain_timing.restype = ctypes.c_int
         L.vmc_chain_timing.argtypes = [ctypes.c_int]
         L.vmc_chain_time.restype = ctypes.c_int
@@ -297,6 +311,82 @@ def grow_hidden(m, params, new_dh, seed, noise_std, m_mom=None, v_mom=None):
     return p1, to
 
 
+def row_tile_options(m):
+    """Row-tile heights the model shape can run with (built-in first)."""
+    opts = (ctypes.c_int32 * 2)()
+    n = ctypes.c_int32(0)
+    _check(lib().vmc_row_tile_options(ctypes.byref(m), opts, ctypes.byref(n)))
+    return [opts[i] for i in range(n.value)]
+
+
+def set_tuning(m, row_tile=0, chain_wgs_per_cu=0):
+    """Set the launch choices of this model shape (0 = built-in); reset_tuning restores all."""
+    _check(lib().vmc_set_tuning(ctypes.byref(m), ctypes.byref(Tuning(int(row_tile), int(chain_wgs_per_cu)))))
+
+
+def reset_tuning(m):
+    _check(lib().vmc_set_tuning(ctypes.byref(m), None))
+
+
+def get_tuning(m):
+    """The launch choices in effect for this model shape, as a dict."""
+    t = Tuning()
+    _check(lib().vmc_get_tuning(ctypes.byref(m), ctypes.byref(t)))
+    return {"row_tile": t.row_tile, "chain_wgs_per_cu": t.chain_wgs_per_cu}
+
+
+def autotune_step(m, params, H, ns, seed=0, counter=0, uniforms=None, ws=None, out=None, reps=3):
+    """Autotuner: times vmc_step under each candidate launch choice, keeps the
+    fastest in the library's table and returns (outputs of vmc_step, choice)."""
+    _dev(params, torch.float32, "params")
+    dev = params.device
+    if uniforms is not None:
+        _dev(uniforms, torch.float32, "uniforms")
+    if out is None:
+        out = (torch.empty((ns, m.N), dtype=torch.uint8, device=dev),
+               torch.empty(ns, dtype=torch.float32, device=dev),
+               torch.empty(ns, dtype=torch.float32, device=dev),
+               torch.empty((ns, 2), dtype=torch.float64, device=dev),
+               torch.empty(param_count(m), dtype=torch.float64, device=dev),
+               torch.empty(4, dtype=torch.float64, device=dev))
+    cfg, lp, ph, e, g, st = out
+    buf, nb = _ws(ws, m, H, ns)
+    t = Tuning()
+    _check(lib().vmc_autotune_step(ctypes.byref(m), _ptr(params), ctypes.byref(H), ns, seed, counter,
+                                   _ptr(uniforms), _ptr(cfg), _ptr(lp), _ptr(ph), _ptr(e), _ptr(g), _ptr(st),
+                                   _ptr(buf), nb, _stream(), int(reps), ctypes.byref(t)))
+    return out, {"row_tile": t.row_tile, "chain_wgs_per_cu": t.chain_wgs_per_cu}
+
+
+def _shape_key(m):
+    return "d%d_%dx%d_h%d_p%d_g%d_c%d" % (m.dims, m.Lx, m.Ly, m.d_h, m.precision, m.glu, m.is_complex)
+
+
+def save_tuning(path, models):
+    """Write the tuning in effect for each model shape to a JSON cache file."""
+    import json
+    data = {_shape_key(m): get_tuning(m) for m in models}
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+
+
+def load_tuning(path, models):
+    """Apply the cached tuning of every listed model shape found in the file;
+    returns the number applied."""
+    import json
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        data = json.load(f)
+    n = 0
+    for m in models:
+        t = data.get(_shape_key(m))
+        if t is not None:
+            set_tuning(m, t["row_tile"], t["chain_wgs_per_cu"])
+            n += 1
+    return n
+
+
 def chain_timing(enable):
     """Start (and reset) or stop event timing of the suffix-chain launch."""
     _check(lib().vmc_chain_timing(int(bool(enable))))
@@ -357,6 +447,24 @@ class StepBatch:
                              counter=pb.get("counter", 0), ws=self.workspaces[i], out=self.outputs[i])
         for s in self.streams:
             main.wait_stream(s)
+
+    def autotune(self, reps=2):
+        """Run the autotuner once per distinct model shape of the batch (on its
+        largest problem, alone on the current stream) before capture; returns
+        {shape: tuning}.  The tuning lives in the library's table, so the
+        captured launches use it."""
+        pick = {}
+        for i, pb in enumerate(self.problems):
+            k = _shape_key(pb["model"])
+            if k not in pick or pb["ns"] > self.problems[pick[k]]["ns"]:
+                pick[k] = i
+        self.tuning = {}
+        for k, i in sorted(pick.items()):
+            pb = self.problems[i]
+            _, self.tuning[k] = autotune_step(pb["model"], pb["params"], pb["ham"], pb["ns"], seed=pb.get("seed", 0),
+                                              counter=pb.get("counter", 0), ws=self.workspaces[i],
+                                              out=self.outputs[i], reps=reps)
+        return self.tuning
 
     def run_eager(self):
         self._issue()

@@ -32,7 +32,8 @@ def lib():
 def test_exports_every_declared_symbol(lib):
     names = declared()
     assert set(names) == {"vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "rnn_logpsi_grad",
-                          "local_energy", "vmc_grad", "vmc_step", "grow_hidden", "vmc_chain_timing",
+                          "local_energy", "vmc_grad", "vmc_step", "grow_hidden", "vmc_row_tile_options",
+                          "vmc_set_tuning", "vmc_get_tuning", "vmc_autotune_step", "vmc_chain_timing",
                           "vmc_chain_time", "vmc_status_str"}
     L = ctypes.CDLL(LIB)
     for n in names:
@@ -95,6 +96,14 @@ def test_argument_errors_before_launch(lib):
     assert L.grow_hidden(ctypes.byref(m), fake, 8, 0, 0.0, fake, None, None, None, None, None) == -1
     assert L.grow_hidden(ctypes.byref(m), fake, 32, 0, -1.0, fake, None, None, None, None, None) == -1
     assert L.grow_hidden(ctypes.byref(m), fake, 32, 0, 0.0, fake, fake, None, None, None, None) == -1
+    # autotuner: repetition count, workspace and outputs checked before any event or launch
+    t = lib.Tuning()
+    args = (ctypes.byref(m), fake, ctypes.byref(H), 100, 0, 0, None, fake, fake, None, fake, fake, fake)
+    assert L.vmc_autotune_step(*args, ws, need, None, 0, ctypes.byref(t)) == -1
+    assert L.vmc_autotune_step(*args, ws, need, None, 101, ctypes.byref(t)) == -1
+    assert L.vmc_autotune_step(*args, ws, need - 1, None, 3, ctypes.byref(t)) == -3
+    assert L.vmc_autotune_step(ctypes.byref(m), fake, ctypes.byref(H), 100, 0, 0, None, None, fake, None, fake,
+                               fake, fake, ws, need, None, 3, ctypes.byref(t)) == -1
     assert L.vmc_status_str(-3) == b"workspace too small"
 
 
@@ -105,3 +114,44 @@ def test_workspace_grows_with_samples(lib):
     assert b > 5 * a
     Hh = lib.ham(lib.VMC_HEISENBERG, 1.0, 0.0, True)
     assert lib.workspace_size(m, Hh, 1000) >= a
+
+
+def test_tuning_table(lib):
+    """Row-tile options, set/get/reset of the tuning table and its argument
+    checks (host-only calls); the workspace size does not depend on it."""
+    m = lib.model(dims=2, Lx=10, Ly=10, d_h=128, glu=True, precision=lib.VMC_BF16)
+    H = lib.ham(lib.VMC_TFIM, 1.0, 3.0)
+    assert lib.row_tile_options(m) == [48, 64]
+    assert lib.get_tuning(m) == {"row_tile": 48, "chain_wgs_per_cu": 2}
+    need = lib.workspace_size(m, H, 10000)
+    lib.set_tuning(m, row_tile=64, chain_wgs_per_cu=4)
+    try:
+        assert lib.get_tuning(m) == {"row_tile": 64, "chain_wgs_per_cu": 4}
+        assert lib.workspace_size(m, H, 10000) == need
+        # another shape is untouched
+        m2 = lib.model(dims=2, Lx=10, Ly=10, d_h=128, glu=True, precision=lib.VMC_FP32)
+        assert lib.get_tuning(m2) == {"row_tile": 32, "chain_wgs_per_cu": 2}
+        assert lib.row_tile_options(m2) == [32, 16]
+        for bad in [dict(row_tile=40), dict(chain_wgs_per_cu=5), dict(chain_wgs_per_cu=-1)]:
+            with pytest.raises(lib.VmcError) as e:
+                lib.set_tuning(m, **bad)
+            assert e.value.status == -1
+        # a rejected call leaves the table as it was
+        assert lib.get_tuning(m) == {"row_tile": 64, "chain_wgs_per_cu": 4}
+    finally:
+        lib.reset_tuning(m)
+    assert lib.get_tuning(m) == {"row_tile": 48, "chain_wgs_per_cu": 2}
+    # shapes without an alternative tile: one option
+    m3 = lib.model(dims=1, Lx=20, d_h=16, precision=lib.VMC_BF16)
+    assert lib.row_tile_options(m3) == [64]
+    # the tuning cache file round trip
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tuning.json")
+        lib.set_tuning(m, row_tile=64, chain_wgs_per_cu=1)
+        lib.save_tuning(path, [m, m3])
+        lib.reset_tuning(m)
+        assert lib.load_tuning(path, [m, m3]) == 2
+        assert lib.get_tuning(m) == {"row_tile": 64, "chain_wgs_per_cu": 1}
+        lib.reset_tuning(m)
+        lib.reset_tuning(m3)
