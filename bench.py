@@ -88,7 +88,7 @@ def build_params(torch, V, synth):
     return p1
 
 
-def run_gpu(torch, V, params, precision, steps, warmup):
+def run_gpu(torch, V, params, precision, steps, warmup, tune=True):
     m = V.model(dims=2, Lx=LX, Ly=LY, d_h=DH, glu=True,
                 precision=V.VMC_BF16 if precision == "bf16" else V.VMC_FP32)
     H = V.ham(V.VMC_TFIM, J=J_COUP, h=H_FIELD)
@@ -105,6 +105,10 @@ def run_gpu(torch, V, params, precision, steps, warmup):
     def step(i):
         V.vmc_step(m, params, H, NS, seed=1, counter=i, ws=ws, out=(cfg, lp, ph, e, g, st))
 
+    # launch choices from the autotuner (untimed set-up; no choice changes a result bit)
+    tuning = None
+    if tune:
+        _, tuning = V.autotune_step(m, params, H, NS, seed=1, counter=0, ws=ws, out=(cfg, lp, ph, e, g, st), reps=2)
     for i in range(warmup):
         step(i)
     torch.cuda.synchronize()
@@ -122,7 +126,7 @@ def run_gpu(torch, V, params, precision, steps, warmup):
     V.chain_timing(False)
     ms = t0.elapsed_time(t1) / steps
     # the configurations and energies of the last step, for the accuracy check
-    return dict(ms_per_step=ms, wall_s=wall, chain_ms=chain_ms / max(launches, 1), launches=launches,
+    return dict(ms_per_step=ms, wall_s=wall, chain_ms=chain_ms / max(launches, 1), launches=launches, tuning=tuning,
                 cfg=cfg.clone(), e=e.clone(), stats=st.clone(), counter=warmup + steps - 1)
 
 
@@ -156,6 +160,7 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=768)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="built-in launch choices instead of the autotuner's")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -175,11 +180,11 @@ def main():
     params = build_params(torch, V, synth)
     torch.cuda.synchronize()
     print("bench: params ready (%d floats), timing BF16 path" % params.numel(), file=sys.stderr, flush=True)
-    bf = run_gpu(torch, V, params, "bf16", args.steps, args.warmup)
+    bf = run_gpu(torch, V, params, "bf16", args.steps, args.warmup, tune=not args.no_tune)
     print("bench: bf16 %.2f ms/step" % bf["ms_per_step"], file=sys.stderr, flush=True)
     fp = None
     if not args.no_fp32:
-        fp = run_gpu(torch, V, params, "fp32", max(1, min(args.steps, 3)), 1)
+        fp = run_gpu(torch, V, params, "fp32", max(1, min(args.steps, 3)), 1, tune=not args.no_tune)
         print("bench: fp32 %.2f ms/step" % fp["ms_per_step"], file=sys.stderr, flush=True)
 
     flops_chain = NS * (N * (N - 1) // 2) * site_flops(DH)
@@ -209,12 +214,13 @@ def main():
                      "flops_per_launch": flops_chain, "avg_launch_ms": round(bf["chain_ms"], 3)},
         "step_flops_algorithmic": flops_step,
         "step_frac_of_bf16_peak": round(flops_step / (bf["ms_per_step"] * 1e-3) / 1e12 / PEAK_TF["bf16"], 4),
+        "tuning": bf["tuning"],
     }
     if fp is not None:
         out["fp32"] = {"value": round(NS / (fp["ms_per_step"] * 1e-3), 1), "ms_per_step": round(fp["ms_per_step"], 3),
                        "chain_avg_launch_ms": round(fp["chain_ms"], 3),
                        "chain_frac_of_fp32_peak": round(flops_chain / (fp["chain_ms"] * 1e-3) / 1e12 / PEAK_TF["fp32"], 4),
-                       "bf16_speedup": round(fp["ms_per_step"] / bf["ms_per_step"], 3)}
+                       "bf16_speedup": round(fp["ms_per_step"] / bf["ms_per_step"], 3), "tuning": fp["tuning"]}
     if not args.no_cpu:
         cb, err_bf = cpu_baseline(torch, params, bf["cfg"], bf["e"], args.cpu_samples)
         out["cpu_baseline"] = cb
