@@ -147,7 +147,8 @@ static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
     w.E = put((size_t)ESLOTS * d.DH * 4);
     w.Hd = put((size_t)4 * d.DH * 4);
     w.hc = put(16);
-    w.hcache = put((size_t)d.N * ns * d.DH * 4);
+    // FP32 prefix states: not kept for 2D bfloat16 (only the operand copy is read)
+    w.hcache = put(d.dims == 2 && d.prec == VMC_BF16 ? 16 : (size_t)d.N * ns * d.DH * 4);
     w.hcs = d.prec == VMC_BF16 ? put((size_t)d.N * ns * d.DH * 2) : w.hcache;
     w.postab = put((size_t)d.N * 16);
     w.lpc = put((size_t)ns * d.N * 2 * 4);
@@ -180,7 +181,7 @@ static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
     // backward
     const int nd_cell = d.dims == 1 ? 4 * d.DH : 3 * d.DH;
     w.nsp = nsp;
-    w.act = put((size_t)d.N * act_feats(d.dims) * d.DH * w.nsp * 4);
+    w.act = put((size_t)d.N * act_feats(d.dims) * d.DH * w.nsp * es);
     w.lgT = put((size_t)d.N * 4 * w.nsp * 4);
     w.hT = put((size_t)d.N * d.DH * w.nsp * es);
     w.gT = put(d.glu ? (size_t)d.N * d.DH * w.nsp * es : 16);
@@ -371,7 +372,7 @@ static vmc_status grad_from_cache(const Dims &d, const WsMap &w, void *ws, int64
     b.ns = ns;
     b.cfg = configs;
     b.hcache = at<float>(ws, w.hcache);
-    b.act = at<float>(ws, w.act);
+    b.act = at<void>(ws, w.act);
     b.lgT = at<float>(ws, w.lgT);
     b.eloc = eloc;
     b.weights = weights;
@@ -429,7 +430,7 @@ vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const u
     FwdArgs a = base_args(d, ws, w, ns);
     a.cfg_in = configs;
     a.hcache = at<float>(ws, w.hcache);
-    a.act = at<float>(ws, w.act);
+    a.act = at<void>(ws, w.act);
     a.lgT = at<float>(ws, w.lgT);
     a.hT = at<void>(ws, w.hT);
     a.gT = at<void>(ws, w.gT);
@@ -453,7 +454,7 @@ vmc_status rnn_logpsi_grad(const vmc_model *m, const float *params, int64_t nc, 
     FwdArgs a = base_args(d, ws, w, nc);
     a.cfg_in = configs;
     a.hcache = at<float>(ws, w.hcache);
-    a.act = at<float>(ws, w.act);
+    a.act = at<void>(ws, w.act);
     a.lgT = at<float>(ws, w.lgT);
     a.hT = at<void>(ws, w.hT);
     a.gT = at<void>(ws, w.gT);
@@ -488,7 +489,7 @@ vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, i
     a.lpc = at<float>(ws, w.lpc);
     a.phc = at<float>(ws, w.phc);
     a.pre = at<double2>(ws, w.pre);
-    a.act = at<float>(ws, w.act);
+    a.act = at<void>(ws, w.act);
     a.lgT = at<float>(ws, w.lgT);
     a.hT = at<void>(ws, w.hT);
     a.gT = at<void>(ws, w.gT);

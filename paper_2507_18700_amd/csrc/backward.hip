@@ -28,7 +28,7 @@ struct BwdArgs {
     const float *Hd;
     int64_t ns, nsp;
     const uint8_t *cfg;
-    const float *act;       // [N][NF*DH][nsp] FP32 gate values and GLU pre-activations
+    const void *act;        // [N][NF*DH][nsp] gate values and GLU pre-activations (store_t)
     const float *lgT;       // [N][4][nsp] logits
     const float *hcache;    // [N][ns][DH] FP32 hidden states (1D: h_{n-1} of the update-gate term)
     const double *eloc, *w, *stats;
@@ -157,7 +157,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
     auto feat = [&](int q, int f, int u, int rb) -> float4 {  // 4 samples of one activation feature
         const int64_t s0 = srow0(rb);
         if (s0 >= nsp) return make_float4(0.f, 0.f, 0.f, 0.f);
-        return *(const float4 *)&a.act[((int64_t)q * NF * DH + f * DH + u) * nsp + s0];
+        const int64_t o = ((int64_t)q * NF * DH + f * DH + u) * nsp + s0;
+        if (VEC == 4) return *(const float4 *)((const float *)a.act + o);
+        const uint2 v = *(const uint2 *)((const uint16_t *)a.act + o);  // 4 bfloat16 samples
+        return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xFFFF0000u),
+                           __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xFFFF0000u));
     };
 
     for (int q = N - 1; q >= 0; q--) {

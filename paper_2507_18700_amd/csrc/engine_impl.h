@@ -451,8 +451,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 if (!glu) head_part(ub, hq, p0, p1, p2, p3);
                 if (STORE) {
                     if (s >= 0 && store_h) {
-                        *(float4 *)&a.hcache[((int64_t)qc * ns_c + s) * DH + u0] =
-                            make_float4(hq[0], hq[1], hq[2], hq[3]);
+                        // FP32 states: read by the 1D chains and 1D backward, and the
+                        // operand copy itself at FP32; 2D bfloat16 reads only the copy
+                        if (DIMS == 1 || VEC == 4)
+                            *(float4 *)&a.hcache[((int64_t)qc * ns_c + s) * DH + u0] =
+                                make_float4(hq[0], hq[1], hq[2], hq[3]);
                         if (VEC == 8) put4<P>((T *)a.hcs + ((int64_t)qc * ns_c + s) * DH + u0, hq);
                     }
                     const int64_t sx = e0 + r;
@@ -462,8 +465,8 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                             ((T *)a.hT)[((int64_t)qc * DH + u0 + i) * a.nsp + sx] = cvt<P>(hq[i]);
 #pragma unroll
                             for (int f = 0; f < NA; f++)
-                                a.act[((int64_t)qc * (NA + 2) * DH + f * DH + u0 + i) * a.nsp + sx] =
-                                    gv[STORE ? f : 0][i];
+                                ((T *)a.act)[((int64_t)qc * (NA + 2) * DH + f * DH + u0 + i) * a.nsp + sx] =
+                                    cvt<P>(gv[STORE ? f : 0][i]);
                         }
                     }
                 }
@@ -492,9 +495,9 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 #pragma unroll
                     for (int i = 0; i < 4; i++) {
                         ((T *)a.gT)[((int64_t)qg * DH + u0 + i) * a.nsp + sx] = cvt<P>(ok ? g[i] : 0.f);
-                        float *fa = &a.act[((int64_t)qg * (NA + 2) * DH + NA * DH + u0 + i) * a.nsp + sx];
-                        fa[0] = ok ? a1[i] : 0.f;
-                        fa[(int64_t)DH * a.nsp] = ok ? a2[i] : 0.f;
+                        T *fa = (T *)a.act + ((int64_t)qg * (NA + 2) * DH + NA * DH + u0 + i) * a.nsp + sx;
+                        fa[0] = cvt<P>(ok ? a1[i] : 0.f);
+                        fa[(int64_t)DH * a.nsp] = cvt<P>(ok ? a2[i] : 0.f);
                     }
                 }
             }

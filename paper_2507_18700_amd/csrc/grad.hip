@@ -81,7 +81,14 @@ struct DwArgs {
     float *part;          // [N*nchunk][Mp][Kp]
     int nchunk;           // sample chunks per position (split of the contraction)
     int64_t chunk;        // samples per chunk (multiple of 32)
+    int units;            // N * nchunk (position, chunk) pairs
+    int tiles_m, tiles;   // output tiles along M, per unit
 };
+
+// Work-groups are handed to the XCDs round-robin by linear id; the output
+// tiles of one (position, chunk) unit read the same delta rows and inputs, so
+// they are given ids on one XCD (id = xcd + kXcds * slot) and share its L2.
+constexpr int kXcds = 8;
 
 // Source row of input column k of segment seg at position q: a hidden state
 // (h or g) of some position, one of the extra rows (bias 1, one-hots), or
@@ -133,8 +140,12 @@ __global__ __launch_bounds__(256) void dw_mfma(DwArgs a) {
     typedef typename P::store_t T;
     constexpr int VEC = P::VEC, KS = P::KSTEP;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, lq = lane >> 4;
-    const int m0 = blockIdx.x * DW_TILE + (w >> 1) * 64, k0 = blockIdx.y * DW_TILE + (w & 1) * 64;
-    const int q = blockIdx.z / a.nchunk, cidx = blockIdx.z - q * a.nchunk;
+    const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+    const int u = xcd + kXcds * (slot / a.tiles);
+    if (u >= a.units) return;  // padding of the last slots (no barrier in this kernel)
+    const int t = slot % a.tiles, mt = t % a.tiles_m, kt = t / a.tiles_m;
+    const int m0 = mt * DW_TILE + (w >> 1) * 64, k0 = kt * DW_TILE + (w & 1) * 64;
+    const int q = u / a.nchunk, cidx = u - q * a.nchunk;
     const int64_t nsp = a.nsp;
     const int64_t sbeg = (int64_t)cidx * a.chunk, send = min(nsp, sbeg + a.chunk);
     const T *A = (const T *)a.A + (int64_t)q * a.MD * nsp;
@@ -182,14 +193,15 @@ __global__ __launch_bounds__(256) void dw_mfma(DwArgs a) {
         }
     };
     uint4 fa[2][4], fb[2][4];
-    load(sbeg, fa[0], fb[0]);
-    for (int64_t s0 = sbeg; s0 < send; s0 += 2 * KS) {
+    const bool any_m = mon[0] || mon[1] || mon[2] || mon[3];
+    if (any_m) load(sbeg, fa[0], fb[0]);
+    for (int64_t s0 = sbeg; any_m && s0 < send; s0 += 2 * KS) {
         load(s0 + KS, fa[1], fb[1]);
         step(fa[0], fb[0]);
         load(s0 + 2 * KS, fa[0], fb[0]);
         step(fa[1], fb[1]);
     }
-    float *out = a.part + (int64_t)blockIdx.z * a.Mp * a.Kp;
+    float *out = a.part + (int64_t)u * a.Mp * a.Kp;
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -343,8 +355,8 @@ void grad_sizes(const Dims &d, int64_t ns, size_t *part_floats) {
 
 template <class P>
 static void launch_dw_p(const DwArgs &a, const SegDims &sd, hipStream_t st) {
-    dim3 grd(sd.Mp / DW_TILE, sd.Kp / DW_TILE, a.d.N * a.nchunk);
-    hipLaunchKernelGGL(dw_mfma<P>, grd, dim3(256), 0, st, a);
+    const int per_xcd = (a.units + kXcds - 1) / kXcds;
+    hipLaunchKernelGGL(dw_mfma<P>, dim3(kXcds * per_xcd * a.tiles), dim3(256), 0, st, a);
 }
 
 hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st);
@@ -384,6 +396,9 @@ hipError_t launch_grad(const GradBufs &b, hipStream_t st) {
         a.part = b.part;
         a.nchunk = dw_chunks(d, sd, a.nsp);
         a.chunk = ((a.nsp + a.nchunk - 1) / a.nchunk + 31) / 32 * 32;
+        a.units = d.N * a.nchunk;
+        a.tiles_m = sd.Mp / DW_TILE;
+        a.tiles = a.tiles_m * (sd.Kp / DW_TILE);
         if (d.prec == VMC_BF16) launch_dw_p<BF16>(a, sd, st);
         else launch_dw_p<F32>(a, sd, st);
         const int rg = sd.MD * ((sd.K + 5 + 31) / 32);

@@ -24,7 +24,7 @@ struct FwdArgs {
     const int4 *postab;      // [N] facts of each order position (build_postab)
     float *lpc, *phc;        // [ns][N][2] log-conditionals, phase conditionals
     double2 *pre;            // [ns][N] running (log P, phase) after each position, FP64
-    float *act;              // [N][NF*DH][nsp] gate and GLU pre-activations for the backward (FP32)
+    void *act;               // [N][NF*DH][nsp] gate and GLU pre-activations for the backward (store_t)
     float *lgT;              // [N][4][nsp] logits (l0, l1, z0, z1) for the backward
     void *hT, *gT;           // with act: transposed h and GLU output [N][DH][nsp] (store_t)
     int64_t nsp;             // sample stride of the transposed arrays
@@ -49,7 +49,8 @@ struct GradBufs {
     const float *E, *Hd;
     int64_t ns;
     const uint8_t *cfg;
-    const float *hcache, *act, *lgT;
+    const float *hcache, *lgT;
+    const void *act;  // store_t
     const double *eloc, *weights;
     const float *coef_lp, *coef_ph;  // given per-sample coefficients (vector-Jacobian product), or NULL
     double *stats;
