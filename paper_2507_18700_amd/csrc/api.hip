@@ -17,7 +17,7 @@ hipError_t launch_forward(const FwdArgs &a, int mode, int store_h, int store_lpc
 hipError_t launch_sched(int ham_kind, int Lx, int Ly, int64_t ns, const uint8_t *cfg, int *cnt,
                         int *list_off, int *list, int *tile_start, int *tile_counter, int MT,
                         hipStream_t st);
-hipError_t launch_assemble(const vmc_ham &H, int Lx, int Ly, int64_t ns, const uint8_t *cfg,
+hipError_t launch_assemble(const vmc_ham &H, int cplx, int Lx, int Ly, int64_t ns, const uint8_t *cfg,
                            const float *lpc, const float *phc, const double2 *pre, const double2 *dsuf, int NC,
                            double *eloc, hipStream_t st);
 int engine_kpx(const Dims &d);
@@ -354,7 +354,7 @@ static vmc_status eloc_from_cache(const Dims &d, const WsMap &w, void *ws, const
         if (hipEventRecord(g_timing.ev[2 * g_timing.n + 1], st) != hipSuccess) return VMC_EDEVICE;
         g_timing.n++;
     }
-    return hip_status(launch_assemble(*H, d.Lx, d.Ly, ns, configs, at<float>(ws, w.lpc), at<float>(ws, w.phc),
+    return hip_status(launch_assemble(*H, d.cplx, d.Lx, d.Ly, ns, configs, at<float>(ws, w.lpc), at<float>(ws, w.phc),
                                       at<double2>(ws, w.pre), at<double2>(ws, w.dsuf), w.NC, eloc, st));
 }
 

@@ -255,16 +255,20 @@ __global__ void tile_scan(int N, int MT, const int *cnt, int *tile_start) {
 //       [lpc[p][sigma'_p] - lpc[p][sigma_p]]              (head at p)
 //     + [chain sum after p] - [original sum after p]     (suffix)
 // halved for |psi|; the original suffix sum is pre[N-1] - pre[p] (FP64).
-// One thread per sample, FP64 sums in fixed connection order.
-__global__ void eloc_assemble(int ham_kind, int marshall, double J, double hx, int Lx, int Ly,
-                              int64_t ns, const uint8_t *cfg, const float *lpc, const float *phc,
-                              const double2 *pre, const double2 *dsuf, int NC, double *eloc) {
-    const int N = Lx * Ly, nb = bond_count(Lx, Ly);
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < ns;
-         s += (int64_t)gridDim.x * blockDim.x) {
+// FP64 sums in a fixed order (see below).
+__global__ __launch_bounds__(256) void eloc_assemble(int ham_kind, int marshall, int cplx, double J, double hx, int Lx,
+                                                     int Ly, int64_t ns, const uint8_t *cfg, const float *lpc,
+                                                     const float *phc, const double2 *pre, const double2 *dsuf, int NC,
+                                                     double *eloc) {
+    // 16 lanes per sample, each over every 16th connection (and bond of the
+    // diagonal), then a fixed butterfly over the 16 lanes: lane 0's sum has
+    // a fixed order, so the result is bitwise reproducible
+    const int N = Lx * Ly, nb = bond_count(Lx, Ly), sub = threadIdx.x & 15;
+    const int64_t step = ((int64_t)gridDim.x * blockDim.x) >> 4;
+    for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4; s < ns; s += step) {
         const uint8_t *c = cfg + s * N;
         double diag = 0.0, ore = 0.0, oim = 0.0;
-        for (int b = 0; b < nb; b++) {
+        for (int b = sub; b < nb; b += 16) {
             int sa, sc;
             bond_sites(b, Lx, Ly, sa, sc);
             diag += (c[sa] == c[sc]) ? 1.0 : -1.0;
@@ -272,6 +276,8 @@ __global__ void eloc_assemble(int ham_kind, int marshall, double J, double hx, i
         const float *lr = lpc + s * N * 2, *pr = phc + s * N * 2;
         const double2 *pp = pre + s * N;
         const double2 tot = pp[N - 1];
+        // psi(sigma')/psi(sigma) of the connection whose first changed order
+        // position is p: the flipped conditional at p, then the chain's suffix
         auto ratio = [&](int p, double2 chain, double coef) {
             const int sg = c[order_site(p, Lx)];
             double dl = (double)lr[2 * p + (1 - sg)] - (double)lr[2 * p + sg];
@@ -281,16 +287,18 @@ __global__ void eloc_assemble(int ham_kind, int marshall, double J, double hx, i
                 dp += chain.y - (tot.y - pp[p].y);
             }
             const double mag = exp(0.5 * dl);
-            ore += coef * mag * cos(dp);
-            oim += coef * mag * sin(dp);
+            if (cplx) {
+                ore += coef * mag * cos(dp);
+                oim += coef * mag * sin(dp);
+            } else {
+                ore += coef * mag;  // a positive RNN has no phase
+            }
         };
         if (ham_kind == 0) {
-            diag *= -J;
-            for (int p = 0; p < N; p++) ratio(p, p < N - 1 ? dsuf[s * NC + p] : make_double2(0.0, 0.0), -hx);
+            for (int p = sub; p < N; p += 16) ratio(p, p < N - 1 ? dsuf[s * NC + p] : make_double2(0.0, 0.0), -hx);
         } else {
-            diag *= 0.25 * J;
             const double jx = (marshall ? -0.5 : 0.5) * J;
-            for (int b = 0; b < nb; b++) {
+            for (int b = sub; b < nb; b += 16) {
                 int sa, sc;
                 bond_sites(b, Lx, Ly, sa, sc);
                 if (c[sa] == c[sc]) continue;
@@ -298,8 +306,16 @@ __global__ void eloc_assemble(int ham_kind, int marshall, double J, double hx, i
                 ratio(pa < pc ? pa : pc, dsuf[s * NC + b], jx);
             }
         }
-        eloc[2 * s] = diag + ore;
-        eloc[2 * s + 1] = oim;
+#pragma unroll
+        for (int m = 8; m >= 1; m >>= 1) {
+            diag += __shfl_xor(diag, m, 16);
+            ore += __shfl_xor(ore, m, 16);
+            oim += __shfl_xor(oim, m, 16);
+        }
+        if (sub == 0) {
+            eloc[2 * s] = diag * (ham_kind == 0 ? -J : 0.25 * J) + ore;
+            eloc[2 * s + 1] = oim;
+        }
     }
 }
 
@@ -342,12 +358,12 @@ hipError_t launch_sched(int ham_kind, int Lx, int Ly, int64_t ns, const uint8_t 
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(const vmc_ham &H, int Lx, int Ly, int64_t ns, const uint8_t *cfg,
+hipError_t launch_assemble(const vmc_ham &H, int cplx, int Lx, int Ly, int64_t ns, const uint8_t *cfg,
                            const float *lpc, const float *phc, const double2 *pre, const double2 *dsuf, int NC,
                            double *eloc, hipStream_t st) {
-    int grid = (int)((ns + 255) / 256);
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(eloc_assemble, dim3(grid), dim3(256), 0, st, H.kind, H.marshall, H.J, H.h, Lx, Ly, ns,
+    int64_t g = (ns * 16 + 255) / 256;
+    const int grid = (int)(g < 1 ? 1 : g > 65536 ? 65536 : g);
+    hipLaunchKernelGGL(eloc_assemble, dim3(grid), dim3(256), 0, st, H.kind, H.marshall, cplx, H.J, H.h, Lx, Ly, ns,
                        cfg, lpc, phc, pre, dsuf, NC, eloc);
     return hipGetLastError();
 }
