@@ -16,7 +16,8 @@
 
 namespace vmc {
 
-constexpr int DW_TILE = 128;    // output tile of the weight-gradient contraction
+constexpr int DW_TILE = 128;            // padding granule of the weight-gradient partials
+constexpr int DW_NF = 9, DW_COLS = 144;  // input-column fragments / columns per contraction tile
 
 // ------------------------------------------------------------- statistics
 
@@ -130,87 +131,125 @@ __global__ void build_extras(Dims d, int64_t ns, int64_t nsp, const uint8_t *cfg
     }
 }
 
-// dW[m][k] at one position q, over one chunk of samples (grid z = q * nchunk
-// + chunk): sum over samples of A[q][m][s] X[q][k][s] on MFMA, operands read
-// as 16-byte fragments straight from memory, the next k-step's fragments in
-// flight while the current one's MFMAs run.  128x128 output tile, 4 waves as
-// 2x2 of 64x64.
-template <class P>
-__global__ __launch_bounds__(256) void dw_mfma(DwArgs a) {
+// dW[m][k] at one position q over one chunk of samples: the sum over samples
+// of A[q][m][s] X[q][k][s] on MFMA.  A work-group of 8 waves covers 128*MF
+// delta rows (MF 16-row fragments per wave, read straight from memory, the
+// next k-step's in flight) against one tile of DW_COLS input columns that the
+// whole work-group stages in LDS (double-buffered), so each input row is read
+// from memory once per row tile instead of once per wave.
+template <class P, int MF>
+__global__ __launch_bounds__(512) void dw_mfma(DwArgs a) {
     typedef typename P::store_t T;
     constexpr int VEC = P::VEC, KS = P::KSTEP;
+    constexpr int LDB = KS + 16 / (int)sizeof(T);  // padded row of the staged input tile
+    constexpr int CPR = KS / VEC;                  // 16-byte chunks per staged row
+    constexpr int NCH = DW_COLS * CPR, CPT = (NCH + 511) / 512;
+    __shared__ __align__(16) T sB[2][DW_COLS * LDB];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, lq = lane >> 4;
     const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
     const int u = xcd + kXcds * (slot / a.tiles);
-    if (u >= a.units) return;  // padding of the last slots (no barrier in this kernel)
-    const int t = slot % a.tiles, mt = t % a.tiles_m, kt = t / a.tiles_m;
-    const int m0 = mt * DW_TILE + (w >> 1) * 64, k0 = kt * DW_TILE + (w & 1) * 64;
+    if (u >= a.units) return;  // padding slot: the whole work-group leaves before any barrier
+    const int t = slot % a.tiles, mt = t % a.tiles_m, nt = t / a.tiles_m;
     const int q = u / a.nchunk, cidx = u - q * a.nchunk;
     const int64_t nsp = a.nsp;
     const int64_t sbeg = (int64_t)cidx * a.chunk, send = min(nsp, sbeg + a.chunk);
+    const int m0 = (mt * 8 + w) * 16 * MF, k0 = nt * DW_COLS;
     const T *A = (const T *)a.A + (int64_t)q * a.MD * nsp;
     const T *X = (const T *)(a.seg == 2 && a.d.glu ? a.gT : a.hT);
     const T *XE = (const T *)a.xT;
-    const T *ap[4];
-    const T *bp[4];
-    bool mon[4], kon[4];
+    const T *ap[MF];
+    bool mon[MF];
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < MF; i++) {
         const int m = m0 + 16 * i + l16;
         mon[i] = (m0 + 16 * i) < a.MD;
         ap[i] = A + (int64_t)(m < a.MD ? m : 0) * nsp + VEC * lq;
-        bool extra;
-        const int k = k0 + 16 * i + l16;
-        const int64_t off = dw_source(a, q, k, extra);
-        // a 16-column block is live if any of its columns has a source
+    }
+    // staging chunks of this thread: row j of the tile, 16-byte part c
+    const T *bsrc[CPT];
+    int bdst[CPT];
+#pragma unroll
+    for (int i = 0; i < CPT; i++) {
+        const int ch = tid + 512 * i, j = ch / CPR, c = ch - j * CPR;
+        bsrc[i] = nullptr;
+        bdst[i] = -1;
+        if (ch < NCH) {
+            bool extra;
+            const int64_t off = dw_source(a, q, k0 + j, extra);
+            if (off >= 0) bsrc[i] = (extra ? XE : X) + off + VEC * c;
+            bdst[i] = j * LDB + VEC * c;
+        }
+    }
+    // input-column fragments with at least one source
+    bool kon[DW_NF];
+#pragma unroll
+    for (int f = 0; f < DW_NF; f++) {
         bool live = false;
         for (int c = 0; c < 16; c++) {
-            bool ex2;
-            live |= dw_source(a, q, k0 + 16 * i + c, ex2) >= 0;
+            bool ex;
+            live |= dw_source(a, q, k0 + 16 * f + c, ex) >= 0;
         }
-        kon[i] = live;
-        bp[i] = off >= 0 ? (extra ? XE : X) + off + VEC * lq : nullptr;
+        kon[f] = live;
     }
-    f32x4_t acc[4][4];
+    f32x4_t acc[MF][DW_NF];
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int i = 0; i < MF; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    auto load = [&](int64_t s0, uint4 *af, uint4 *bf) {
+        for (int f = 0; f < DW_NF; f++) acc[i][f] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    uint4 stg[CPT];
+    auto gload_b = [&](int64_t s0) {
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            af[i] = (mon[i] && s0 < send) ? *(const uint4 *)(ap[i] + s0) : make_uint4(0, 0, 0, 0);
-            bf[i] = (bp[i] && s0 < send) ? *(const uint4 *)(bp[i] + s0) : make_uint4(0, 0, 0, 0);
-        }
+        for (int i = 0; i < CPT; i++)
+            stg[i] = (bsrc[i] && s0 < send) ? *(const uint4 *)(bsrc[i] + s0) : make_uint4(0, 0, 0, 0);
     };
-    auto step = [&](const uint4 *af, const uint4 *bf) {
+    auto sstore_b = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            if (!mon[i]) continue;
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                if (kon[j]) P::mma(acc[i][j], af[i], bf[j]);
-        }
+        for (int i = 0; i < CPT; i++)
+            if (bdst[i] >= 0) *(uint4 *)&sB[buf][bdst[i]] = stg[i];
     };
-    uint4 fa[2][4], fb[2][4];
-    const bool any_m = mon[0] || mon[1] || mon[2] || mon[3];
-    if (any_m) load(sbeg, fa[0], fb[0]);
-    for (int64_t s0 = sbeg; any_m && s0 < send; s0 += 2 * KS) {
-        load(s0 + KS, fa[1], fb[1]);
-        step(fa[0], fb[0]);
-        load(s0 + 2 * KS, fa[0], fb[0]);
-        step(fa[1], fb[1]);
+    auto load_a = [&](int64_t s0, uint4 *fa) {
+#pragma unroll
+        for (int i = 0; i < MF; i++)
+            fa[i] = (mon[i] && s0 < send) ? *(const uint4 *)(ap[i] + s0) : make_uint4(0, 0, 0, 0);
+    };
+    // one k-step on buffer buf with fragments fa; the next k-step's loads
+    // (into fn and the other buffer) are issued before the MFMAs
+    auto body = [&](int64_t s0, int buf, const uint4 *fa, uint4 *fn) {
+        const bool more = s0 + KS < send;  // uniform over the work-group
+        if (more) {
+            gload_b(s0 + KS);
+            load_a(s0 + KS, fn);
+        }
+#pragma unroll
+        for (int f = 0; f < DW_NF; f++) {
+            if (!kon[f]) continue;
+            const uint4 bf = *(const uint4 *)&sB[buf][(16 * f + l16) * LDB + VEC * lq];
+#pragma unroll
+            for (int i = 0; i < MF; i++)
+                if (mon[i]) P::mma(acc[i][f], fa[i], bf);
+        }
+        if (more) sstore_b(buf ^ 1);
+        __syncthreads();
+    };
+    uint4 fa0[MF], fa1[MF];
+    gload_b(sbeg);
+    sstore_b(0);
+    load_a(sbeg, fa0);
+    __syncthreads();
+    for (int64_t s0 = sbeg; s0 < send; s0 += 2 * KS) {
+        body(s0, 0, fa0, fa1);
+        if (s0 + KS < send) body(s0 + KS, 1, fa1, fa0);
     }
     float *out = a.part + (int64_t)u * a.Mp * a.Kp;
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int i = 0; i < MF; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++)
+        for (int f = 0; f < DW_NF; f++)
 #pragma unroll
             for (int ii = 0; ii < 4; ii++) {
-                const int m = m0 + i * 16 + 4 * lq + ii;
-                const int k = k0 + j * 16 + l16;
-                out[(int64_t)m * a.Kp + k] = acc[i][j][ii];
+                const int m = m0 + 16 * i + 4 * lq + ii;
+                const int k = k0 + 16 * f + l16;
+                if (m < a.MD && k < a.Kp) out[(int64_t)m * a.Kp + k] = acc[i][f][ii];
             }
 }
 
@@ -331,12 +370,29 @@ static SegDims seg_dims(const Dims &d, int seg) {
 
 int64_t grad_nsp(int64_t ns) { return (ns + 31) / 32 * 32; }
 
-// Sample chunks per position of the weight-gradient contraction: enough
-// work-groups to fill the chip several times over, chunks of >= 512 samples.
+// Delta-row fragments per wave (1..3) for MD delta rows: the fewest padded
+// rows, then the larger fragment count; tiles along M and along the inputs.
+static int dw_mf(int MD) {
+    int best = 3, waste = 1 << 30;
+    for (int mf = 3; mf >= 1; mf--) {
+        const int rows = 128 * mf, wst = (MD + rows - 1) / rows * rows - MD;
+        if (wst < waste) {
+            waste = wst;
+            best = mf;
+        }
+    }
+    return best;
+}
+static int dw_tiles_m(const SegDims &s) { return (s.MD + 128 * dw_mf(s.MD) - 1) / (128 * dw_mf(s.MD)); }
+static int dw_tiles_n(const SegDims &s) { return (s.K + 5 + DW_COLS - 1) / DW_COLS; }
+
+// Sample chunks per position of the weight-gradient contraction: about 768
+// work-groups in all (three rounds of the chip), chunks of >= 1024 samples,
+// at most 16.
 static int dw_chunks(const Dims &d, const SegDims &s, int64_t nsp) {
-    const int64_t tiles = (int64_t)(s.Mp / DW_TILE) * (s.Kp / DW_TILE) * d.N;
-    int64_t c = (4096 + tiles - 1) / tiles;
-    const int64_t cmax = nsp / 512 > 1 ? nsp / 512 : 1;
+    const int64_t tiles = (int64_t)dw_tiles_m(s) * dw_tiles_n(s) * d.N;
+    int64_t c = (768 + tiles - 1) / tiles;
+    const int64_t cmax = nsp / 1024 > 1 ? nsp / 1024 : 1;
     if (c > cmax) c = cmax;
     if (c > 16) c = 16;
     return (int)(c < 1 ? 1 : c);
@@ -355,8 +411,12 @@ void grad_sizes(const Dims &d, int64_t ns, size_t *part_floats) {
 
 template <class P>
 static void launch_dw_p(const DwArgs &a, const SegDims &sd, hipStream_t st) {
-    const int per_xcd = (a.units + kXcds - 1) / kXcds;
-    hipLaunchKernelGGL(dw_mfma<P>, dim3(kXcds * per_xcd * a.tiles), dim3(256), 0, st, a);
+    const dim3 grid(kXcds * ((a.units + kXcds - 1) / kXcds) * a.tiles);
+    switch (dw_mf(sd.MD)) {
+        case 1: hipLaunchKernelGGL((dw_mfma<P, 1>), grid, dim3(512), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((dw_mfma<P, 2>), grid, dim3(512), 0, st, a); break;
+        default: hipLaunchKernelGGL((dw_mfma<P, 3>), grid, dim3(512), 0, st, a); break;
+    }
 }
 
 hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st);
@@ -397,8 +457,8 @@ hipError_t launch_grad(const GradBufs &b, hipStream_t st) {
         a.nchunk = dw_chunks(d, sd, a.nsp);
         a.chunk = ((a.nsp + a.nchunk - 1) / a.nchunk + 31) / 32 * 32;
         a.units = d.N * a.nchunk;
-        a.tiles_m = sd.Mp / DW_TILE;
-        a.tiles = a.tiles_m * (sd.Kp / DW_TILE);
+        a.tiles_m = dw_tiles_m(sd);
+        a.tiles = a.tiles_m * dw_tiles_n(sd);
         if (d.prec == VMC_BF16) launch_dw_p<BF16>(a, sd, st);
         else launch_dw_p<F32>(a, sd, st);
         const int rg = sd.MD * ((sd.K + 5 + 31) / 32);
