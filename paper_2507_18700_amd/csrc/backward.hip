@@ -18,6 +18,8 @@
 // weight-gradient contraction.  Tiles, waves and weight residency follow the
 // forward engine: bfloat16 up to d_h = 128 keeps the transposed weights in
 // registers (8 waves at 128).
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace vmc {
@@ -154,17 +156,45 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
 
     // first sample of this lane's 4-row group in row block rb (transposed arrays)
     auto srow0 = [&](int rb) -> int64_t { return e0 + wr * C::RW + rb * 16 + 4 * lq; };
-    auto feat = [&](int q, int f, int u, int rb) -> float4 {  // 4 samples of one activation feature
+    // 4 samples of one activation feature as stored (FP32: float4; bfloat16:
+    // 4 halves in a uint2, widened at use), so that every feature of a position
+    // can be in flight from the start of the position at half the registers
+    typedef typename std::conditional<VEC == 4, float4, uint2>::type RawF;
+    auto feat = [&](int q, int f, int u, int rb) -> RawF {
         const int64_t s0 = srow0(rb);
-        if (s0 >= nsp) return make_float4(0.f, 0.f, 0.f, 0.f);
-        const int64_t o = ((int64_t)q * NF * DH + f * DH + u) * nsp + s0;
-        if (VEC == 4) return *(const float4 *)((const float *)a.act + o);
-        const uint2 v = *(const uint2 *)((const uint16_t *)a.act + o);  // 4 bfloat16 samples
-        return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xFFFF0000u),
-                           __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xFFFF0000u));
+        if (s0 >= nsp) {
+            if constexpr (VEC == 4) return make_float4(0.f, 0.f, 0.f, 0.f);
+            else return make_uint2(0u, 0u);
+        }
+        return *(const RawF *)((const T *)a.act + ((int64_t)q * NF * DH + f * DH + u) * nsp + s0);
     };
+    auto widen = [](RawF v) -> float4 {
+        if constexpr (VEC == 4) {
+            return v;
+        } else {
+            return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xFFFF0000u),
+                               __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xFFFF0000u));
+        }
+    };
+    // logits of the next position (rows of lanes tid < MT), loaded one position ahead
+    float lgn[4] = {0.f, 0.f, 0.f, 0.f};
+    auto load_lg = [&](int q) {
+        const int s = tid < MT ? sRow[tid] : -1;
+        if (s >= 0) {
+            const float *lg = a.lgT + (int64_t)q * 4 * nsp + s;
+            lgn[0] = lg[0];
+            lgn[1] = lg[nsp];
+            if (cplx) {
+                lgn[2] = lg[2 * nsp];
+                lgn[3] = lg[3 * nsp];
+            }
+        }
+    };
+    load_lg(N - 1);
 
     for (int q = N - 1; q >= 0; q--) {
+        const float lgc[4] = {lgn[0], lgn[1], lgn[2], lgn[3]};
+        if (q > 0) load_lg(q - 1);
         const int site = order_site(q, Lx);
         const int jrow = q / Lx, icol = site - jrow * Lx;
         const bool row_start = (q % Lx) == 0;
@@ -172,8 +202,9 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
         const bool has_vt = DIMS == 2 && jrow > 0;
         const bool vt_succ_parked = DIMS == 2 && jrow + 1 < Ly && !last_in_row;
 
-        // GLU pre-activations of this step, in flight during the head phase
-        float4 fa1[RB][UB], fa2[RB][UB];
+        // GLU pre-activations and gate values of this step, in flight during
+        // the head and GLU phases
+        RawF fa1[RB][UB], fa2[RB][UB];
         if (glu) {
 #pragma unroll
             for (int rb = 0; rb < RB; rb++)
@@ -185,13 +216,13 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
                 }
         }
 
+
         // (a) head deltas
         if (tid < MT) {
             const int s = sRow[tid];
             float d0 = 0.f, d1 = 0.f, z0 = 0.f, z1 = 0.f;
             if (s >= 0) {
-                const float *lg = a.lgT + (int64_t)q * 4 * nsp + s;
-                const float l0 = lg[0], l1 = lg[nsp];
+                const float l0 = lgc[0], l1 = lgc[1];
                 const int sg = sSig[tid * N + site];
                 const float p1 = rcpf_(1.0f + __expf(l0 - l1));  // softmax(l)[1]
                 const float p0 = 1.0f - p1;
@@ -199,7 +230,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
                 d0 = ca * ((sg == 0 ? 1.f : 0.f) - p0);
                 d1 = ca * ((sg == 1 ? 1.f : 0.f) - p1);
                 if (cplx) {
-                    const float z = sg ? lg[3 * nsp] : lg[2 * nsp];
+                    const float z = sg ? lgc[3] : lgc[2];
                     const float den = 1.0f + fabsf(z);
                     const float dz = sCoef[tid][1] * PI_F / (den * den);
                     if (sg) z1 = dz;
@@ -236,8 +267,9 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
                 for (int ub = 0; ub < UB; ub++) {
                     const int u = wu * C::UW + ub * 16 + l16;
                     float d1[4], d2[4];
-                    const float a1v[4] = {fa1[rb][ub].x, fa1[rb][ub].y, fa1[rb][ub].z, fa1[rb][ub].w};
-                    const float a2v[4] = {fa2[rb][ub].x, fa2[rb][ub].y, fa2[rb][ub].z, fa2[rb][ub].w};
+                    const float4 w1 = widen(fa1[rb][ub]), w2 = widen(fa2[rb][ub]);
+                    const float a1v[4] = {w1.x, w1.y, w1.z, w1.w};
+                    const float a2v[4] = {w2.x, w2.y, w2.z, w2.w};
 #pragma unroll
                     for (int ii = 0; ii < 4; ii++) {
                         const float sg2 = sigmoidf_(a2v[ii]);
@@ -290,7 +322,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
 #pragma unroll
             for (int rb = 0; rb < RB; rb++)
 #pragma unroll
-                for (int ub = 0; ub < UB; ub++) fc[f][rb][ub] = feat(q, f, wu * C::UW + ub * 16 + l16, rb);
+                for (int ub = 0; ub < UB; ub++) fc[f][rb][ub] = widen(feat(q, f, wu * C::UW + ub * 16 + l16, rb));
         float4 fhp[DIMS == 1 ? RB : 1][DIMS == 1 ? UB : 1];  // 1D: h_{n-1} (FP32)
         if (DIMS == 1) {
 #pragma unroll
