@@ -25,6 +25,7 @@ size_t engine_lds(const Dims &d);
 int forward_tile_rows(const Dims &d);
 int chain_tile_rows(const Dims &d);
 int row_tile_options(const Dims &d, int out[2]);
+int chain_occupancy(const Dims &d);
 int backward_tile_rows(int DH);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
 hipError_t launch_grad(const GradBufs &b, hipStream_t st);
@@ -59,13 +60,30 @@ static int padded_dh(int d) {
 // Launch choices per model shape, process-wide.  Every choice gives the same
 // result bits (rows are computed independently of their tile and of the
 // work-group that runs them), so the table only changes speed.
-static const int kChainWpcDefault = 2, kChainWpcMax = 4;
+static const int kChainWpcFallback = 2, kChainWpcMax = 4;
 typedef std::array<int, 7> ShapeKey;
 static std::mutex g_tune_mu;
 static std::map<ShapeKey, vmc_tuning> g_tune;
 
 static ShapeKey shape_key(const vmc_model *m) {
     return ShapeKey{m->dims, m->Lx, m->dims == 2 ? m->Ly : 1, m->d_h, m->precision, m->glu, m->is_complex};
+}
+
+// Built-in work-groups per CU of the chain launch: as many as fit one CU
+// (a persistent launch), queried once per shape; 2 if the runtime cannot say.
+static std::map<std::array<int, 4>, int> g_occ;
+static int default_chain_wpc(const Dims &d) {
+    const std::array<int, 4> k{d.prec, d.dims, d.DH, d.N};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_occ.find(k);
+        if (it != g_occ.end()) return it->second;
+    }
+    int n = chain_occupancy(d);
+    n = n < 1 ? kChainWpcFallback : n > kChainWpcMax ? kChainWpcMax : n;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_occ[k] = n;
+    return n;
 }
 
 static vmc_tuning lookup_tuning(const vmc_model *m) {
@@ -90,14 +108,14 @@ static Dims make_dims(const vmc_model *m) {
     d.glu = m->glu;
     d.prec = m->precision;
     d.row_alt = 0;
-    d.chain_wpc = kChainWpcDefault;
+    d.chain_wpc = 0;
     const vmc_tuning t = lookup_tuning(m);
     if (t.row_tile > 0) {
         int opt[2];
         const int n = row_tile_options(d, opt);
         d.row_alt = n > 1 && t.row_tile == opt[1];
     }
-    if (t.chain_wgs_per_cu > 0) d.chain_wpc = t.chain_wgs_per_cu;
+    d.chain_wpc = t.chain_wgs_per_cu > 0 ? t.chain_wgs_per_cu : default_chain_wpc(d);
     return d;
 }
 

@@ -9,6 +9,18 @@ hipError_t launch_engine_bf16_2d(const FwdArgs &a, int mode, int sh, int sl, int
 hipError_t launch_engine_f32_1d(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st);
 hipError_t launch_engine_f32_2d(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st);
 
+int chain_occupancy_bf16_1d(int DH, int N);
+int chain_occupancy_bf16_2d(int DH, int N);
+int chain_occupancy_f32_1d(int DH, int N);
+int chain_occupancy_f32_2d(int DH, int N);
+
+// Work-groups of the suffix-chain launch per compute unit (0: unknown).
+int chain_occupancy(const Dims &d) {
+    if (d.prec == VMC_BF16)
+        return d.dims == 1 ? chain_occupancy_bf16_1d(d.DH, d.N) : chain_occupancy_bf16_2d(d.DH, d.N);
+    return d.dims == 1 ? chain_occupancy_f32_1d(d.DH, d.N) : chain_occupancy_f32_2d(d.DH, d.N);
+}
+
 hipError_t launch_forward(const FwdArgs &a, int mode, int store_h, int store_lpc, int store_act, int grid,
                           hipStream_t st) {
     if (a.d.prec == VMC_BF16)

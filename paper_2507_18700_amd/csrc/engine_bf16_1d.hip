@@ -7,4 +7,6 @@ hipError_t launch_engine_bf16_1d(const FwdArgs &a, int mode, int sh, int sl, int
     return launch_engine_d<BF16, 1>(a, mode, sh, sl, sa, grid, st);
 }
 
+int chain_occupancy_bf16_1d(int DH, int N) { return chain_occupancy_d<BF16, 1>(DH, N); }
+
 }  // namespace vmc

@@ -7,4 +7,6 @@ hipError_t launch_engine_f32_1d(const FwdArgs &a, int mode, int sh, int sl, int 
     return launch_engine_d<F32, 1>(a, mode, sh, sl, sa, grid, st);
 }
 
+int chain_occupancy_f32_1d(int DH, int N) { return chain_occupancy_d<F32, 1>(DH, N); }
+
 }  // namespace vmc

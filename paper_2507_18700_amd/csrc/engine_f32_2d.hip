@@ -7,4 +7,6 @@ hipError_t launch_engine_f32_2d(const FwdArgs &a, int mode, int sh, int sl, int 
     return launch_engine_d<F32, 2>(a, mode, sh, sl, sa, grid, st);
 }
 
+int chain_occupancy_f32_2d(int DH, int N) { return chain_occupancy_d<F32, 2>(DH, N); }
+
 }  // namespace vmc

@@ -112,7 +112,8 @@ __device__ inline uint16_t cvt<BF16>(float x) { return __builtin_bit_cast(uint16
 // Facts of one order position (the position table, see build_postab).
 struct PosInfo {
     int site, site_hz, site_vt, pos_vt, icol;
-    bool colw;  // h of this position is a later vertical input (kept in the column buffer)
+    int colw;  // h of this position is a later vertical input (kept in the column buffer);
+               // an int, so that the struct has no padding bytes to copy through private memory
 };
 
 template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF, int TC>
@@ -351,19 +352,23 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
         auto vt_needed = [&](int qn, const PosInfo &pi) __attribute__((always_inline)) {
             return DIMS == 2 && pi.site_vt >= 0 && pi.pos_vt < qn - 1;
         };
+        // (chunk e of a tile is row e / (DH / VEC), columns (e % (DH / VEC)) * VEC:
+        // offset e * VEC in a row-major [MT][DH] block, so the column buffer is
+        // addressed as a uniform base plus a 32-bit per-lane offset)
         auto vt_issue = [&](const PosInfo &pi) __attribute__((always_inline)) {
             const bool cache = pi.pos_vt <= p;
+            const T *cb = colbuf + (int64_t)pi.icol * (MT * DH);
 #pragma unroll
             for (int i = 0; i < PF; i++) {
                 const int e = tid + i * NT;
                 if (e < NCH) {
-                    const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
                     if (cache) {
+                        const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
                         const int s = sRow[r];
                         pfv[i] = s >= 0 ? *(const uint4 *)&hcs[((int64_t)pi.pos_vt * ns_c + s) * DH + c]
                                         : make_uint4(0, 0, 0, 0);
                     } else {
-                        pfv[i] = *(const uint4 *)&colbuf[((int64_t)pi.icol * MT + r) * DH + c];
+                        pfv[i] = *(const uint4 *)(cb + (uint32_t)(e * VEC));
                     }
                 }
             }
@@ -380,9 +385,10 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
         };
         // h of position qn into the column buffer (its column's next vertical input)
         auto col_copy = [&](int qn, const PosInfo &pi) __attribute__((always_inline)) {
+            T *cb = colbuf + (int64_t)pi.icol * (MT * DH);
             for (int e = tid; e < NCH; e += NT) {
                 const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
-                *(uint4 *)&colbuf[((int64_t)pi.icol * MT + r) * DH + c] = *(const uint4 *)&sH[qn & 1][r * H_LD + c];
+                *(uint4 *)(cb + (uint32_t)(e * VEC)) = *(const uint4 *)&sH[qn & 1][r * H_LD + c];
             }
         };
         // indicator columns of position qn, one row per lane of wave iw (one 16-byte store):
@@ -833,6 +839,32 @@ static hipError_t launch_engine_d(const FwdArgs &a, int mode, int sh, int sl, in
     }
 #undef VMC_ENG
     return hipErrorInvalidValue;
+}
+
+// Work-groups of the suffix-chain launch that fit one compute unit (its
+// registers, LDS and waves), or 0 if the runtime cannot say.
+template <class P, int DIMS>
+static int chain_occupancy_d(int DH, int N) {
+#define VMC_OCC(DHV)                                                                                         \
+    {                                                                                                        \
+        typedef Eng<P, DIMS, DHV, Pick<P, DHV>::NW, 1> C;                                                    \
+        const size_t dyn = ((size_t)C::MT * N + 15) / 16 * 16;                                              \
+        int nb = 0;                                                                                          \
+        const void *f = (const void *)rnn_engine<P, DIMS, DHV, Pick<P, DHV>::NW, Pick<P, DHV>::REGW, 0, 1, 1>; \
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess ||    \
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, Pick<P, DHV>::NW * 64, dyn) != hipSuccess)  \
+            return 0;                                                                                        \
+        return nb;                                                                                           \
+    }
+    switch (DH) {
+        case 16: VMC_OCC(16)
+        case 32: VMC_OCC(32)
+        case 64: VMC_OCC(64)
+        case 128: VMC_OCC(128)
+        case 256: VMC_OCC(256)
+    }
+#undef VMC_OCC
+    return 0;
 }
 
 // rows per tile of tile class TC (2: 0 where no alternative exists)

@@ -122,7 +122,8 @@ def test_tuning_table(lib):
     m = lib.model(dims=2, Lx=10, Ly=10, d_h=128, glu=True, precision=lib.VMC_BF16)
     H = lib.ham(lib.VMC_TFIM, 1.0, 3.0)
     assert lib.row_tile_options(m) == [48, 64]
-    assert lib.get_tuning(m) == {"row_tile": 48, "chain_wgs_per_cu": 2}
+    builtin = lib.get_tuning(m)  # the chain default comes from the occupancy query (2 without a GPU)
+    assert builtin["row_tile"] == 48 and 1 <= builtin["chain_wgs_per_cu"] <= 4
     need = lib.workspace_size(m, H, 10000)
     lib.set_tuning(m, row_tile=64, chain_wgs_per_cu=4)
     try:
@@ -130,7 +131,7 @@ def test_tuning_table(lib):
         assert lib.workspace_size(m, H, 10000) == need
         # another shape is untouched
         m2 = lib.model(dims=2, Lx=10, Ly=10, d_h=128, glu=True, precision=lib.VMC_FP32)
-        assert lib.get_tuning(m2) == {"row_tile": 32, "chain_wgs_per_cu": 2}
+        assert lib.get_tuning(m2)["row_tile"] == 32
         assert lib.row_tile_options(m2) == [32, 16]
         for bad in [dict(row_tile=40), dict(chain_wgs_per_cu=5), dict(chain_wgs_per_cu=-1)]:
             with pytest.raises(lib.VmcError) as e:
@@ -140,7 +141,7 @@ def test_tuning_table(lib):
         assert lib.get_tuning(m) == {"row_tile": 64, "chain_wgs_per_cu": 4}
     finally:
         lib.reset_tuning(m)
-    assert lib.get_tuning(m) == {"row_tile": 48, "chain_wgs_per_cu": 2}
+    assert lib.get_tuning(m) == builtin
     # shapes without an alternative tile: one option
     m3 = lib.model(dims=1, Lx=20, d_h=16, precision=lib.VMC_BF16)
     assert lib.row_tile_options(m3) == [64]
