@@ -121,6 +121,9 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                                                       int store_act_) {
     // cache writes exist only in the STORE variant (the chain kernel has none)
     const int store_h = STORE && store_h_, store_lpc = STORE && store_lpc_, store_act = STORE && store_act_;
+    // the launch mode is fixed by the instantiation: the chain tile class runs
+    // MODE_CHAIN only, TF = 0 is sampling, TF = 1 otherwise (see launch_engine_t)
+    constexpr bool CHAIN = TC == 1;
     typedef Eng<P, DIMS, DH, NW, TC> C;
     typedef typename P::store_t T;
     constexpr int MT = C::MT, RB = C::RB, UB = C::UB, KS = C::KS, VEC = P::VEC;
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
         // ---------------------------------------------------------- tile
         int p = -1, nrow;
         int64_t e0;
-        if (mode == MODE_CHAIN) {
+        if (CHAIN) {
             __syncthreads();
             if (tid == 0) sTile = atomicAdd(a.tile_counter, 1);
             __syncthreads();
@@ -282,7 +285,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
         if (tid < MT) {
             if (tid < nrow) {
                 const int64_t ent = e0 + tid;
-                if (mode != MODE_CHAIN) {
+                if (!CHAIN) {
                     my_s = (int)ent;
                 } else if (a.ham_kind == 0) {
                     my_s = (int)ent;
@@ -303,10 +306,10 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
         for (int e = tid; e < MT * N; e += NT) {
             const int r = e / N, c = e - r * N;
             const int s = sRow[r];
-            sSig[e] = (s >= 0 && mode != MODE_SAMPLE) ? a.cfg_in[(int64_t)s * N + c] : (uint8_t)0;
+            sSig[e] = (s >= 0 && TF) ? a.cfg_in[(int64_t)s * N + c] : (uint8_t)0;
         }
         __syncthreads();
-        if (tid < MT && my_s >= 0 && mode == MODE_CHAIN) {
+        if (tid < MT && my_s >= 0 && CHAIN) {
             sSig[tid * N + f1] ^= 1;
             if (f2 >= 0) sSig[tid * N + f2] ^= 1;
         }
@@ -356,7 +359,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
         // offset e * VEC in a row-major [MT][DH] block, so the column buffer is
         // addressed as a uniform base plus a 32-bit per-lane offset)
         auto vt_issue = [&](const PosInfo &pi) __attribute__((always_inline)) {
-            const bool cache = pi.pos_vt <= p;
+            const bool cache = CHAIN && pi.pos_vt <= p;
             const T *cb = colbuf + (int64_t)pi.icol * (MT * DH);
 #pragma unroll
             for (int i = 0; i < PF; i++) {
@@ -665,7 +668,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             const float ph0 = cplx ? PI_F * softsignf_(z0) : 0.f;
             const float ph1 = cplx ? PI_F * softsignf_(z1) : 0.f;
             int sg;
-            if (mode == MODE_SAMPLE) {
+            if (!TF) {
                 float uni;
                 if (a.uniforms) {
                     uni = a.uniforms[(int64_t)s * N + qf];
@@ -767,14 +770,14 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
         if (tid < MT && sRow[tid] >= 0) {
             const int s = sRow[tid];
             const double2 acc = sAcc[tid];
-            if (mode == MODE_CHAIN) {
+            if (CHAIN) {
                 a.dsuf[(int64_t)s * a.NC + sCid[tid]] = acc;
             } else {
                 if (a.logp) a.logp[s] = (float)acc.x;
                 if (a.phase) a.phase[s] = (float)acc.y;
             }
         }
-        if (mode == MODE_SAMPLE) {
+        if (!TF) {
             for (int e = tid; e < MT * N; e += NT) {
                 const int r = e / N, c = e - r * N;
                 const int s = sRow[r];
