@@ -116,7 +116,10 @@ struct PosInfo {
                // an int, so that the struct has no padding bytes to copy through private memory
 };
 
-template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF, int TC>
+// CPX: the complex (phase) head fixed at compile time (0 or 1) or read at run
+// time (-1).  The chain launch is instantiated for both values: without the
+// run-time branches its epilogue basic blocks are larger and better scheduled.
+template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF, int TC, int CPX = -1>
 __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int store_h_, int store_lpc_,
                                                       int store_act_) {
     // cache writes exist only in the STORE variant (the chain kernel has none)
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w / C::WU, wu = w % C::WU;
     const int N = a.d.N, Lx = a.d.Lx, Ly = a.d.Ly;
-    const int cplx = a.d.cplx, glu = a.d.glu;
+    const int cplx = CPX >= 0 ? CPX : a.d.cplx, glu = a.d.glu;
     const T *__restrict__ Bc = (const T *)a.Bc;
     const T *__restrict__ Bg = (const T *)a.Bg;
     const T *__restrict__ hcs = (const T *)a.hcs;
@@ -789,14 +792,14 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 
 // ------------------------------------------------------------ launchers
 
-template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF, int TC>
+template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF, int TC, int CPX = -1>
 static hipError_t launch_engine_s(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
     typedef Eng<P, DIMS, DH, NW, TC> C;
     size_t dyn = ((size_t)C::MT * a.d.N + 15) / 16 * 16;
-    hipError_t e = hipFuncSetAttribute((const void *)rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF, TC>,
+    hipError_t e = hipFuncSetAttribute((const void *)rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF, TC, CPX>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF, TC>), dim3(grid), dim3(NW * 64), dyn, st, a, mode,
+    hipLaunchKernelGGL((rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF, TC, CPX>), dim3(grid), dim3(NW * 64), dyn, st, a, mode,
                        sh, sl, sa);
     return hipGetLastError();
 }
@@ -814,7 +817,9 @@ static hipError_t launch_engine_r(const FwdArgs &a, int mode, int sh, int sl, in
 
 template <class P, int DIMS, int DH, int NW, int REGW>
 static hipError_t launch_engine_t(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
-    if (mode == MODE_CHAIN) return launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, 1>(a, mode, sh, sl, sa, grid, st);
+    if (mode == MODE_CHAIN)
+        return a.d.cplx ? launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, 1, 1>(a, mode, sh, sl, sa, grid, st)
+                        : launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, 1, 0>(a, mode, sh, sl, sa, grid, st);
     if constexpr (Eng<P, DIMS, DH, NW, 2>::HAS_ALT) {
         if (a.d.row_alt) return launch_engine_r<P, DIMS, DH, NW, REGW, 2>(a, mode, sh, sl, sa, grid, st);
     }
@@ -853,7 +858,7 @@ static int chain_occupancy_d(int DH, int N) {
         typedef Eng<P, DIMS, DHV, Pick<P, DHV>::NW, 1> C;                                                    \
         const size_t dyn = ((size_t)C::MT * N + 15) / 16 * 16;                                              \
         int nb = 0;                                                                                          \
-        const void *f = (const void *)rnn_engine<P, DIMS, DHV, Pick<P, DHV>::NW, Pick<P, DHV>::REGW, 0, 1, 1>; \
+        const void *f = (const void *)rnn_engine<P, DIMS, DHV, Pick<P, DHV>::NW, Pick<P, DHV>::REGW, 0, 1, 1, 0>; \
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess ||    \
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, Pick<P, DHV>::NW * 64, dyn) != hipSuccess)  \
             return 0;                                                                                        \
