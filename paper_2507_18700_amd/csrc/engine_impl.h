@@ -524,7 +524,10 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
         // position qc (do_cell, input pattern HZ/VT).  With register-resident
         // weights the MFMAs of the next row block are issued ahead of the
         // epilogue of the current one, across the GLU -> cell boundary too.
-        auto run_phase = [&](bool do_glu, int qg, bool do_cell, int qc, const PosInfo &pc, auto HZ, auto VT) __attribute__((always_inline)) {
+        // `mid` runs once the first MFMAs of the phase are issued (the one-wave
+        // finalisation and indicator work then overlaps the matrix pipe)
+        auto run_phase = [&](bool do_glu, int qg, bool do_cell, int qc, const PosInfo &pc, auto HZ, auto VT,
+                             auto &&mid) __attribute__((always_inline)) {
             constexpr bool hz = decltype(HZ)::value, vt = decltype(VT)::value;
             const bool vt_prev = vt && pc.pos_vt == qc - 1;
             if (REGW) {
@@ -565,6 +568,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 f32x4_t accg[2][2 * UB], accc[2][3 * UB];
                 if (do_glu) {
                     gblock(0, accg[0]);
+                    mid();
 #pragma unroll
                     for (int rb = 0; rb < RB; rb++) {
                         if (rb + 1 < RB) gblock(rb + 1, accg[(rb + 1) & 1]);
@@ -573,6 +577,9 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                     }
                 } else if (do_cell) {
                     cblock(0, accc[0]);
+                    mid();
+                } else {
+                    mid();
                 }
                 if (do_cell) {
 #pragma unroll
@@ -582,6 +589,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                     }
                 }
             } else {
+                mid();
                 if (do_glu) {
                     f32x4_t acc2[RB][2 * UB];
 #pragma unroll
@@ -641,12 +649,12 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
         };
         using T1 = std::integral_constant<bool, true>;
         using T0 = std::integral_constant<bool, false>;
-        auto phase = [&](bool do_glu, int qg, bool do_cell, int qc, const PosInfo &pc) __attribute__((always_inline)) {
+        auto phase = [&](bool do_glu, int qg, bool do_cell, int qc, const PosInfo &pc, auto &&mid) __attribute__((always_inline)) {
             const bool hz = pc.site_hz >= 0, vt = DIMS == 2 && pc.site_vt >= 0;
-            if (!do_cell || (!hz && !vt)) run_phase(do_glu, qg, do_cell, qc, pc, T0{}, T0{});
-            else if (DIMS == 1 || !vt) run_phase(do_glu, qg, do_cell, qc, pc, T1{}, T0{});
-            else if (hz) run_phase(do_glu, qg, do_cell, qc, pc, T1{}, T1{});
-            else run_phase(do_glu, qg, do_cell, qc, pc, T0{}, T1{});
+            if (!do_cell || (!hz && !vt)) run_phase(do_glu, qg, do_cell, qc, pc, T0{}, T0{}, mid);
+            else if (DIMS == 1 || !vt) run_phase(do_glu, qg, do_cell, qc, pc, T1{}, T0{}, mid);
+            else if (hz) run_phase(do_glu, qg, do_cell, qc, pc, T1{}, T1{}, mid);
+            else run_phase(do_glu, qg, do_cell, qc, pc, T0{}, T1{}, mid);
         };
 
         // per-row finalisation of position qf, one row per lane of wave fw:
@@ -724,7 +732,8 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 indicator(P1, (q0 + 1) & 1, NW / 2);
             }
             __syncthreads();
-            phase(false, q0, true, q0, P0);
+            auto nop = []() __attribute__((always_inline)) {};
+            phase(false, q0, true, q0, P0, nop);
             __syncthreads();
             PosInfo Pc = P0, Pp = P0;
             for (int q = q0; q < N; q++) {
@@ -734,12 +743,14 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 const bool vt2 = has_2 && vt_needed(q + 2, P2);
                 if (vt2) vt_issue(P2);
                 if (Pc.colw) col_copy(q, Pc);
-                phase(glu, q, has_next, q + 1, Pn);
-                if (has_2) {
-                    if (vt2) vt_store(q & 1);
-                    indicator(P2, q & 1, (q + 2 + NW / 2) % NW);
-                }
-                if (q > q0) finalize(q - 1, Pp, (q - 1) % NW);
+                // indicator of q+2 (its own buffer) and finalisation of q-1
+                // (head sums complete since the last barrier), each by one wave
+                auto mid = [&]() __attribute__((always_inline)) {
+                    if (has_2) indicator(P2, q & 1, (q + 2 + NW / 2) % NW);
+                    if (q > q0) finalize(q - 1, Pp, (q - 1) % NW);
+                };
+                phase(glu, q, has_next, q + 1, Pn, mid);
+                if (vt2) vt_store(q & 1);
                 __syncthreads();
                 Pp = Pc;
                 Pc = Pn;
@@ -755,11 +766,12 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 const PosInfo Pn = has_next ? pos(q + 1) : Pc;
                 const bool vtn = has_next && vt_needed(q + 1, Pn);
                 if (vtn) vt_issue(Pn);
-                phase(false, q, true, q, Pc);
+                auto nop = []() __attribute__((always_inline)) {};
+                phase(false, q, true, q, Pc, nop);
                 if (vtn) vt_store((q + 1) & 1);
                 __syncthreads();
                 if (Pc.colw) col_copy(q, Pc);
-                if (glu) phase(true, q, false, q, Pc);
+                if (glu) phase(true, q, false, q, Pc, nop);
                 __syncthreads();
                 // the row's lane draws its spin and writes the next indicator
                 finalize(q, Pc, q % NW);
