@@ -152,6 +152,101 @@ def cpu_baseline(torch, params, cfg, e_gpu, n_sub):
                        "re-evaluation + gradient), %.1f s" % (n_sub, NS, dt)), err
 
 
+def _timed(torch, fn, reps):
+    """Milliseconds per call of fn (one call untimed first), HIP events on the current stream."""
+    fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / reps
+
+
+def zigzag_pos(Lx, Ly):
+    """Order position of every lattice site (zig-zag: even rows left to right)."""
+    import numpy as np
+    pos = np.zeros(Lx * Ly, dtype=np.int64)
+    for j in range(Ly):
+        for i in range(Lx):
+            pos[j * Lx + i] = j * Lx + (i if j % 2 == 0 else Lx - 1 - i)
+    return pos
+
+
+def other_workloads(torch, V, synth, reps=3):
+    """The other configurations of the path, each timed as one vmc_step (or
+    the batch graph) after the autotuner; C4 also times local_energy on
+    configurations with 74 % anti-aligned bonds and reports the connection
+    count and the chain kernel's fraction of the bf16 peak."""
+    import numpy as np
+    out = {}
+
+    def step_rate(m, p, H, ns, name, extra=None):
+        ws = V.Workspace()
+        ws.get(V.workspace_size(m, H, ns))
+        res = V.vmc_step(m, p, H, ns, seed=1, counter=0, ws=ws)
+        V.autotune_step(m, p, H, ns, seed=1, counter=0, ws=ws, out=res, reps=1)
+        ms = _timed(torch, lambda: V.vmc_step(m, p, H, ns, seed=1, counter=1, ws=ws, out=res), reps)
+        out[name] = dict(samples_per_s=round(ns / (ms * 1e-3), 1), ms_per_step=round(ms, 3), ns=ns, **(extra or {}))
+        return ws, res
+
+    # C1: 1D TFIM N=20, J=h=1, d_h=16, Ns=1000 (FP32 path)
+    spec = synth.ModelSpec(dims=1, Lx=20, d_h=16)
+    m = V.model(dims=1, Lx=20, d_h=16, precision=V.VMC_FP32)
+    step_rate(m, torch.from_numpy(synth.xavier_params(spec, 0)).cuda(), V.ham(V.VMC_TFIM, 1.0, 1.0), 1000,
+              "c1_tfim1d_N20_dh16_fp32")
+    # C2: 1D Heisenberg N=50 (Marshall), complex RNN d_h 32 -> 64, Ns=10^4 (FP32)
+    spec = synth.ModelSpec(dims=1, Lx=50, d_h=32, is_complex=True)
+    m0 = V.model(dims=1, Lx=50, d_h=32, is_complex=True)
+    p2, m2 = V.grow_hidden(m0, torch.from_numpy(synth.xavier_params(spec, 0)).cuda(), 64, 2, 1e-3)
+    step_rate(m2, p2, V.ham(V.VMC_HEISENBERG, 1.0, 0.0, True), 10000, "c2_heis1d_N50_dh64_cplx_fp32")
+    # C4: 2D Heisenberg 16x16 (Marshall), complex RNN + GLU d_h=256, Ns=4096 (BF16)
+    spec = synth.ModelSpec(dims=2, Lx=16, Ly=16, d_h=256, is_complex=True, glu=True)
+    m4 = V.model(dims=2, Lx=16, Ly=16, d_h=256, is_complex=True, glu=True, precision=V.VMC_BF16)
+    p4 = torch.from_numpy(synth.xavier_params(spec, 0)).cuda()
+    H4 = V.ham(V.VMC_HEISENBERG, 1.0, 0.0, True)
+    ws4, _ = step_rate(m4, p4, H4, 4096, "c4_heis2d_16x16_dh256_cplx_bf16")
+    cfg = synth.neel_like_configs(4096, 16, 16, 5, 0.74)
+    a = cfg.reshape(4096, 16, 16)
+    anti_h, anti_v = a[:, :, 1:] != a[:, :, :-1], a[:, 1:, :] != a[:, :-1, :]
+    pos = zigzag_pos(16, 16).reshape(16, 16)
+    first_h = np.minimum(pos[:, 1:], pos[:, :-1])[None].repeat(4096, 0)
+    first_v = np.minimum(pos[1:, :], pos[:-1, :])[None].repeat(4096, 0)
+    suffix = (255 - first_h)[anti_h].sum() + (255 - first_v)[anti_v].sum()
+    nconn = (anti_h.sum() + anti_v.sum()) / 4096.0
+    dcfg = torch.from_numpy(cfg).cuda()
+    e = V.local_energy(m4, p4, H4, dcfg, ws=ws4)
+    torch.cuda.synchronize()
+    V.chain_timing(True)
+    ms = _timed(torch, lambda: V.local_energy(m4, p4, H4, dcfg, ws=ws4, out=e), reps)
+    chain_ms, launches = V.chain_time()
+    V.chain_timing(False)
+    chain_ms /= max(launches, 1)
+    f_site = 16 * 256 * 256 + 2 * 256 * 4
+    out["c4_local_energy_74pct_anti"] = dict(
+        configs_per_s=round(4096 / (ms * 1e-3), 1), ms=round(ms, 3), mean_connections=round(float(nconn), 1),
+        chain_ms=round(chain_ms, 3),
+        chain_frac_of_bf16_peak=round(float(suffix) * f_site / (chain_ms * 1e-3) / 1e12 / PEAK_TF["bf16"], 4))
+    # C5: 32 uneven 1D TFIM chains (N 32..128, h 0.5..1.5), d_h=64, Ns=2048 each, BF16, one graph
+    problems = []
+    for c, (n, h) in enumerate(synth.uneven_chains(32, 3)):
+        spec = synth.ModelSpec(dims=1, Lx=n, d_h=64)
+        problems.append(dict(model=V.model(dims=1, Lx=n, d_h=64, precision=V.VMC_BF16),
+                             params=torch.from_numpy(synth.xavier_params(spec, 100 + c)).cuda(),
+                             ham=V.ham(V.VMC_TFIM, 1.0, h), ns=2048, seed=1, counter=0))
+    b = V.StepBatch(problems, streams=8)
+    b.run_eager()
+    b.autotune(reps=1)
+    b.capture()
+    ms = _timed(torch, b.replay, reps)
+    out["c5_32_uneven_tfim1d_dh64_bf16"] = dict(samples_per_s=round(32 * 2048 / (ms * 1e-3), 1),
+                                                 ms_per_batch_step=round(ms, 3), chains=32)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +256,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="built-in launch choices instead of the autotuner's")
+    ap.add_argument("--no-other", action="store_true", help="skip the other workloads (C1, C2, C4, C5)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -221,6 +317,9 @@ def main():
                        "chain_avg_launch_ms": round(fp["chain_ms"], 3),
                        "chain_frac_of_fp32_peak": round(flops_chain / (fp["chain_ms"] * 1e-3) / 1e12 / PEAK_TF["fp32"], 4),
                        "bf16_speedup": round(fp["ms_per_step"] / bf["ms_per_step"], 3), "tuning": fp["tuning"]}
+    if not args.no_other:
+        print("bench: other workloads", file=sys.stderr, flush=True)
+        out["other_workloads"] = other_workloads(torch, V, synth)
     if not args.no_cpu:
         cb, err_bf = cpu_baseline(torch, params, bf["cfg"], bf["e"], args.cpu_samples)
         out["cpu_baseline"] = cb

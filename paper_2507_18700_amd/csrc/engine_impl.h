@@ -53,8 +53,10 @@ struct Eng {
     static constexpr int WR = NW / WU;                        // waves along rows
     static constexpr int UW = DH / WU;
     static constexpr int UB = UW / 16;
-    // rows per tile (FP32 tiles at d_h >= 128 are halved to fit the LDS)
-    static constexpr int MT_CHAIN = (DH >= 256 || (P::VEC == 4 && DH >= 128)) ? 32 : 64;
+    // rows per tile (FP32 tiles at d_h >= 128 are halved to fit the LDS;
+    // bfloat16 d_h = 256 with 8 waves: 48, the most that fits)
+    static constexpr int MT_CHAIN =
+        (P::VEC == 4 && DH >= 128) ? 32 : DH >= 256 ? (P::VEC == 8 && NW == 8 ? 48 : 32) : 64;
     static constexpr bool BIG = P::VEC == 8 && DH == 128 && NW == 8;
     static constexpr int MT_ROW = BIG ? 48 : MT_CHAIN;
     static constexpr int MT_ALT = BIG ? 64 : MT_CHAIN / 2;
@@ -599,20 +601,28 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                             acc2[rb][ub] = f32x4_t{gb1[ub][0], gb1[ub][1], gb1[ub][2], gb1[ub][3]};
                             acc2[rb][UB + ub] = f32x4_t{gb2[ub][0], gb2[ub][1], gb2[ub][2], gb2[ub][3]};
                         }
-#pragma unroll 2
-                    for (int kk = 0; kk < KHB; kk += KS) {
-                        uint4 af[RB];
-#pragma unroll
-                        for (int rb = 0; rb < RB; rb++) af[rb] = glu_frag(qg, rb, kk);
+                    // weight fragments stream from L2, one k-step ahead
+                    uint4 gw[2][2 * UB];
+                    auto gwload = [&](int kk, uint4 *w) __attribute__((always_inline)) {
 #pragma unroll
                         for (int g = 0; g < 2; g++)
 #pragma unroll
                             for (int ub = 0; ub < UB; ub++) {
                                 const int n = g * DH + wu * C::UW + ub * 16 + l16;
-                                const uint4 bf = *(const uint4 *)&Bg[(int64_t)n * KHB + kk + VEC * lq];
-#pragma unroll
-                                for (int rb = 0; rb < RB; rb++) P::mma(acc2[rb][g * UB + ub], bf, af[rb]);
+                                w[g * UB + ub] = *(const uint4 *)&Bg[(int64_t)n * KHB + kk + VEC * lq];
                             }
+                    };
+                    gwload(0, gw[0]);
+#pragma unroll
+                    for (int j = 0; j < NKG; j++) {
+                        if (j + 1 < NKG) gwload((j + 1) * KS, gw[(j + 1) & 1]);
+                        uint4 af[RB];
+#pragma unroll
+                        for (int rb = 0; rb < RB; rb++) af[rb] = glu_frag(qg, rb, j * KS);
+#pragma unroll
+                        for (int c = 0; c < 2 * UB; c++)
+#pragma unroll
+                            for (int rb = 0; rb < RB; rb++) P::mma(acc2[rb][c], gw[j & 1][c], af[rb]);
                     }
 #pragma unroll
                     for (int rb = 0; rb < RB; rb++) glu_epi(qg, rb, acc2[rb]);
@@ -623,24 +633,34 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                     for (int rb = 0; rb < RB; rb++)
 #pragma unroll
                         for (int c = 0; c < 3 * UB; c++) acc[rb][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-                    for (int ks = 0; ks < NKS; ks++) {
-                        const int blk = ks / NKB;
-                        const bool is_x = ks == NKS - 1;
-                        if (!is_x && blk == 0 && !hz) continue;
-                        if (!is_x && blk == 1 && !vt) continue;
-                        uint4 af[RB];
-#pragma unroll
-                        for (int rb = 0; rb < RB; rb++) af[rb] = a_frag(qc, vt_prev, rb, ks);
+                    // the k-steps with an input (hz block, vt block, indicator),
+                    // weight fragments streaming from L2 one k-step ahead
+                    constexpr int NH = hz ? NKB : 0, NV = (DIMS == 2 && vt) ? NKB : 0, NACT = NH + NV + 1;
+                    auto ks_of = [&](int j) __attribute__((always_inline)) {
+                        return j < NH ? j : j < NH + NV ? NKB + (j - NH) : NKS - 1;
+                    };
+                    uint4 cw[2][3 * UB];
+                    auto cwload = [&](int ks, uint4 *w) __attribute__((always_inline)) {
 #pragma unroll
                         for (int g = 0; g < 3; g++)
 #pragma unroll
                             for (int ub = 0; ub < UB; ub++) {
                                 const int n = g * DH + wu * C::UW + ub * 16 + l16;
-                                const uint4 bf = *(const uint4 *)&Bc[(int64_t)n * KPX + ks * KS + VEC * lq];
-#pragma unroll
-                                for (int rb = 0; rb < RB; rb++) P::mma(acc[rb][g * UB + ub], bf, af[rb]);
+                                w[g * UB + ub] = *(const uint4 *)&Bc[(int64_t)n * KPX + ks * KS + VEC * lq];
                             }
+                    };
+                    cwload(ks_of(0), cw[0]);
+#pragma unroll
+                    for (int j = 0; j < NACT; j++) {
+                        if (j + 1 < NACT) cwload(ks_of(j + 1), cw[(j + 1) & 1]);
+                        const int ks = ks_of(j);
+                        uint4 af[RB];
+#pragma unroll
+                        for (int rb = 0; rb < RB; rb++) af[rb] = a_frag(qc, vt_prev, rb, ks);
+#pragma unroll
+                        for (int c = 0; c < 3 * UB; c++)
+#pragma unroll
+                            for (int rb = 0; rb < RB; rb++) P::mma(acc[rb][c], cw[j & 1][c], af[rb]);
                     }
 #pragma unroll
                     for (int rb = 0; rb < RB; rb++) cell_epi(qc, pc, rb, acc[rb]);
@@ -843,7 +863,7 @@ static hipError_t launch_engine_t(const FwdArgs &a, int mode, int sh, int sl, in
 template <class P, int DH>
 struct Pick {
     static constexpr int REGW = (P::VEC == 8 && DH <= 128) ? 1 : 0;
-    static constexpr int NW = (REGW && DH == 128) ? 8 : 4;
+    static constexpr int NW = (P::VEC == 8 && DH >= 128) ? 8 : 4;
 };
 
 template <class P, int DIMS>
