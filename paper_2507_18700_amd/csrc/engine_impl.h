@@ -77,7 +77,7 @@ struct Eng {
     // static LDS of the kernel (bytes), for the host-side capacity check
     static constexpr size_t LDS =
         sizeof(typename P::store_t) * ((size_t)2 * MT * H_LD + (DIMS == 2 ? 2 * MT * H_LD : 8) + 2 * MT * X_LD) +
-        4 * ((size_t)NLOG * WU * MT * 4 + 2 * DH) + 8 * MT + 16 * MT + 16;
+        4 * ((size_t)NLOG * WU * MT * 4 + 6 * DH) + 8 * MT + 16 * MT + 16;  // (+ the LDS constants of streamed weights)
 };
 
 // Sums over the four 16-lane groups of two values at once: p ends up summed
@@ -143,6 +143,10 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     __shared__ __align__(16) T sX[2][MT * X_LD];
     __shared__ __align__(16) float sLog[C::NLOG][C::WU][MT][4];
     __shared__ __align__(16) float sHw[2][DH];  // phase-head rows (complex amplitudes)
+    // streamed weights (no REGW): the per-unit GLU biases and amplitude-head
+    // rows live in LDS instead of registers
+    constexpr bool CL = !REGW;
+    __shared__ __align__(16) float sCst[CL ? 4 : 1][CL ? DH : 4];
     __shared__ int sRow[MT], sCid[MT];
     __shared__ double2 sAcc[MT];  // running (log P, phase) of each row, FP64
     __shared__ int sTile;
@@ -169,10 +173,12 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             const int u = unit0(ub) + i;
-            gb1[ub][i] = a.E[E_B1 * DH + u];
-            gb2[ub][i] = a.E[E_B2 * DH + u];
-            hw0[ub][i] = a.Hd[u];
-            hw1[ub][i] = a.Hd[DH + u];
+            if (!CL) {
+                gb1[ub][i] = a.E[E_B1 * DH + u];
+                gb2[ub][i] = a.E[E_B2 * DH + u];
+                hw0[ub][i] = a.Hd[u];
+                hw1[ub][i] = a.Hd[DH + u];
+            }
             if (DIMS == 1) {
                 bin_[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_BIN * DH + u];
                 win0[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_XIN0 * DH + u];
@@ -180,6 +186,24 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             }
         }
     for (int e = tid; e < 2 * DH; e += NT) (&sHw[0][0])[e] = a.Hd[2 * DH + e];
+    if (CL)
+        for (int e = tid; e < 4 * DH; e += NT) {
+            const int k = e / DH, u = e - k * DH;
+            sCst[CL ? k : 0][CL ? u : 0] = k == 0 ? a.E[E_B1 * DH + u] : k == 1 ? a.E[E_B2 * DH + u] : a.Hd[(k - 2) * DH + u];
+        }
+    // constant k (0: GLU bias 1, 1: GLU bias 2, 2, 3: amplitude-head rows) of the lane's 4 units of block ub
+    auto cst4 = [&](int k, int ub, float *v) __attribute__((always_inline)) {
+        if (CL) {
+            const float4 t = *(const float4 *)&sCst[CL ? k : 0][CL ? unit0(ub) : 0];
+            v[0] = t.x;
+            v[1] = t.y;
+            v[2] = t.z;
+            v[3] = t.w;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; i++) v[i] = k == 0 ? gb1[ub][i] : k == 1 ? gb2[ub][i] : k == 2 ? hw0[ub][i] : hw1[ub][i];
+        }
+    };
     for (int e = tid; e < C::NLOG * C::WU * MT * 4; e += NT) (&sLog[0][0][0][0])[e] = 0.f;
     const float hc0 = a.hc[0], hc1 = a.hc[1], hc2 = a.hc[2], hc3 = a.hc[3];
 
@@ -245,10 +269,13 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     };
     // partial head sums of the lane's 4 units of one row
     auto head_part = [&](int ub, const float *g, float &p0, float &p1, float &p2, float &p3) __attribute__((always_inline)) {
+        float w0[4], w1[4];
+        cst4(2, ub, w0);
+        cst4(3, ub, w1);
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            p0 += hw0[ub][i] * g[i];
-            p1 += hw1[ub][i] * g[i];
+            p0 += w0[i] * g[i];
+            p1 += w1[i] * g[i];
         }
         if (cplx) {
             const float4 z0 = *(const float4 *)&sHw[0][unit0(ub)];
@@ -536,8 +563,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 auto gblock = [&](int rb, f32x4_t *acc2) __attribute__((always_inline)) {
 #pragma unroll
                     for (int ub = 0; ub < UB; ub++) {
-                        acc2[ub] = f32x4_t{gb1[ub][0], gb1[ub][1], gb1[ub][2], gb1[ub][3]};
-                        acc2[UB + ub] = f32x4_t{gb2[ub][0], gb2[ub][1], gb2[ub][2], gb2[ub][3]};
+                        float b1[4], b2[4];
+                        cst4(0, ub, b1);
+                        cst4(1, ub, b2);
+                        acc2[ub] = f32x4_t{b1[0], b1[1], b1[2], b1[3]};
+                        acc2[UB + ub] = f32x4_t{b2[0], b2[1], b2[2], b2[3]};
                     }
 #pragma unroll
                     for (int kq = 0; kq < NKG; kq++) {
@@ -598,8 +628,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                     for (int rb = 0; rb < RB; rb++)
 #pragma unroll
                         for (int ub = 0; ub < UB; ub++) {
-                            acc2[rb][ub] = f32x4_t{gb1[ub][0], gb1[ub][1], gb1[ub][2], gb1[ub][3]};
-                            acc2[rb][UB + ub] = f32x4_t{gb2[ub][0], gb2[ub][1], gb2[ub][2], gb2[ub][3]};
+                            float b1[4], b2[4];
+                            cst4(0, ub, b1);
+                            cst4(1, ub, b2);
+                            acc2[rb][ub] = f32x4_t{b1[0], b1[1], b1[2], b1[3]};
+                            acc2[rb][UB + ub] = f32x4_t{b2[0], b2[1], b2[2], b2[3]};
                         }
                     // weight fragments stream from L2, one k-step ahead
                     uint4 gw[2][2 * UB];

@@ -191,31 +191,36 @@ __global__ void build_postab(Dims d, int4 *tab) {
 // Per first-changed position p: capacity offsets of the connection list
 // (Heisenberg) or the row counts (TFIM: every sample, p < N-1), the zeroed
 // counters, and the tile counter.
-__global__ void sched_prep(int ham_kind, int Lx, int Ly, int64_t ns, int *cnt, int *list_off,
-                           int *tile_counter) {
-    const int N = Lx * Ly;
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        *tile_counter = 0;
-        if (ham_kind == 0) {
-            for (int p = 0; p < N; p++) cnt[p] = (p < N - 1) ? (int)ns : 0;
-        } else {
-            const int nb = bond_count(Lx, Ly);
-            int64_t off = 0;
-            for (int p = 0; p < N; p++) {
-                list_off[p] = (int)off;
-                int k = 0;
-                for (int b = 0; b < nb; b++) {
-                    int sa, sc;
-                    bond_sites(b, Lx, Ly, sa, sc);
-                    int pa = site_pos(sa, Lx), pc = site_pos(sc, Lx);
-                    if ((pa < pc ? pa : pc) == p) k++;
-                }
-                off += (int64_t)k * ns;
-                cnt[p] = 0;
-            }
-            list_off[N] = (int)off;
-        }
+__global__ __launch_bounds__(1024) void sched_prep(int ham_kind, int Lx, int Ly, int64_t ns, int *cnt,
+                                                   int *list_off, int *tile_counter) {
+    // one work-group: bonds counted per first changed position in LDS, then
+    // one thread lays out the list offsets (N <= 1024)
+    __shared__ int kb[1025];
+    const int N = Lx * Ly, tid = threadIdx.x;
+    if (tid == 0) *tile_counter = 0;
+    if (ham_kind == 0) {
+        for (int p = tid; p < N; p += blockDim.x) cnt[p] = (p < N - 1) ? (int)ns : 0;
+        return;
     }
+    for (int p = tid; p < N; p += blockDim.x) kb[p] = 0;
+    __syncthreads();
+    const int nb = bond_count(Lx, Ly);
+    for (int b = tid; b < nb; b += blockDim.x) {
+        int sa, sc;
+        bond_sites(b, Lx, Ly, sa, sc);
+        const int pa = site_pos(sa, Lx), pc = site_pos(sc, Lx);
+        atomicAdd(&kb[pa < pc ? pa : pc], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t off = 0;
+        for (int p = 0; p < N; p++) {
+            list_off[p] = (int)off;
+            off += (int64_t)kb[p] * ns;
+        }
+        list_off[N] = (int)off;
+    }
+    for (int p = tid; p < N; p += blockDim.x) cnt[p] = 0;
 }
 
 // Heisenberg: every anti-aligned bond of every sample is one connection,
@@ -346,7 +351,7 @@ hipError_t launch_stage(const Dims &d, const float *prm, void *Bc, void *BcT, vo
 hipError_t launch_sched(int ham_kind, int Lx, int Ly, int64_t ns, const uint8_t *cfg, int *cnt,
                         int *list_off, int *list, int *tile_start, int *tile_counter, int MT,
                         hipStream_t st) {
-    hipLaunchKernelGGL(sched_prep, dim3(1), dim3(64), 0, st, ham_kind, Lx, Ly, ns, cnt, list_off, tile_counter);
+    hipLaunchKernelGGL(sched_prep, dim3(1), dim3(1024), 0, st, ham_kind, Lx, Ly, ns, cnt, list_off, tile_counter);
     if (ham_kind == 1) {
         int64_t total = ns * bond_count(Lx, Ly);
         int grid = (int)((total + 255) / 256);
