@@ -175,8 +175,9 @@ vmc_status grow_hidden(const vmc_model *from, const float *p_from, int32_t new_d
  *                     one of vmc_row_tile_options(); 0 = built-in choice;
  *  chain_wgs_per_cu:  persistent work-groups per compute unit of the
  *                     suffix-chain launch of local_energy, 1..4; 0 = built-in
- *                     (as many as fit one compute unit, from the runtime's
- *                     occupancy query; 2 when it cannot answer).
+ *                     (twice as many as fit one compute unit, from the
+ *                     runtime's occupancy query, at most 4; 2 when it cannot
+ *                     answer).
  * No choice changes any output bit: each row of a tile and each connected
  * configuration is computed independently of the tile and of the work-group
  * that runs it.  vmc_workspace_size() covers every choice, so a workspace
