@@ -257,6 +257,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="built-in launch choices instead of the autotuner's")
     ap.add_argument("--no-other", action="store_true", help="skip the other workloads (C1, C2, C4, C5)")
+    ap.add_argument("--only-other", action="store_true",
+                    help="only the other workloads, printed as their own JSON line (profiling runs)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -273,6 +275,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.only_other:
+        print(json.dumps({"other_workloads": other_workloads(torch, V, synth)}))
+        return
     params = build_params(torch, V, synth)
     torch.cuda.synchronize()
     print("bench: params ready (%d floats), timing BF16 path" % params.numel(), file=sys.stderr, flush=True)
