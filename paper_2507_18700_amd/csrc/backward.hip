@@ -289,6 +289,17 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
         }
         __syncthreads();
 
+        // register-resident weights leave room to load the gate values before the
+        // GLU input-gradient MFMAs (their latency then overlaps that phase)
+        RawF fcr[NA][RB][UB];
+        if (REGW) {
+#pragma unroll
+            for (int f = 0; f < NA; f++)
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                    for (int ub = 0; ub < UB; ub++) fcr[f][rb][ub] = feat(q, f, wu * C::UW + ub * 16 + l16, rb);
+        }
         // (c) GLU input gradient: dh_glu = [d1 | d2] . [W_1 ; W_2] (MFMA)
         f32x4_t accg[RB][UB];
 #pragma unroll
@@ -322,7 +333,8 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
 #pragma unroll
             for (int rb = 0; rb < RB; rb++)
 #pragma unroll
-                for (int ub = 0; ub < UB; ub++) fc[f][rb][ub] = widen(feat(q, f, wu * C::UW + ub * 16 + l16, rb));
+                for (int ub = 0; ub < UB; ub++)
+                    fc[f][rb][ub] = widen(REGW ? fcr[f][rb][ub] : feat(q, f, wu * C::UW + ub * 16 + l16, rb));
         float4 fhp[DIMS == 1 ? RB : 1][DIMS == 1 ? UB : 1];  // 1D: h_{n-1} (FP32)
         if (DIMS == 1) {
 #pragma unroll
