@@ -46,7 +46,9 @@ extern "C" {
 typedef enum {
     VMC_OK = 0,
     VMC_EINVAL = -1,       /* bad argument (null pointer, size, descriptor) */
-    VMC_EUNSUPPORTED = -2, /* valid but not supported (e.g. d_h > 256) */
+    VMC_EUNSUPPORTED = -2, /* valid but not supported: d_h not in {16,32,64,128,256},
+                              or a kernel's LDS (its tile's configurations, tile rows
+                              x N bytes, plus its static tiles) above 160 KiB */
     VMC_ENOSPACE = -3,     /* workspace smaller than vmc_workspace_size() */
     VMC_EDEVICE = -4       /* a HIP call or kernel launch failed */
 } vmc_status;

@@ -27,6 +27,7 @@ int chain_tile_rows(const Dims &d);
 int row_tile_options(const Dims &d, int out[2]);
 int chain_occupancy(const Dims &d);
 int backward_tile_rows(int DH);
+size_t backward_lds(const Dims &d);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
 hipError_t launch_grad(const GradBufs &b, hipStream_t st);
 void grad_sizes(const Dims &d, int64_t ns, size_t *part_floats);
@@ -232,12 +233,9 @@ static vmc_status check_common(const vmc_model *m, const float *params, int64_t 
     if (padded_dh(m->d_h) < 0) return VMC_EUNSUPPORTED;
     if (n >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
     Dims d = make_dims(m);
-    int opt[2];
-    const int nopt = row_tile_options(d, opt);
-    for (int i = 0; i < nopt; i++)
-        if ((int64_t)opt[i] * d.N > 32768) return VMC_EUNSUPPORTED;
-    if ((int64_t)chain_tile_rows(d) * d.N > 32768) return VMC_EUNSUPPORTED;
-    if (engine_lds(d) > kMaxLds) return VMC_EUNSUPPORTED;
+    // every launch's LDS (static tiles plus the tile's configurations, rows x N
+    // bytes) must fit one compute unit, for every tile choice
+    if (engine_lds(d) > kMaxLds || backward_lds(d) > kMaxLds) return VMC_EUNSUPPORTED;
     if (H && H->kind == VMC_HEISENBERG && n * bond_count(d.Lx, d.Ly) >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
     WsMap w = ws_map(d, H, n);
     if (need) *need = w.total;

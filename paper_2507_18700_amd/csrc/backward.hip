@@ -500,6 +500,34 @@ static hipError_t launch_bwd_d(const BwdArgs &a, hipStream_t st) {
 
 int backward_tile_rows(int DH) { return BWD_MT(DH); }
 
+// LDS of one reverse-sweep work-group (static tiles, GLU weights, the tile's
+// configurations), for the host-side capacity check
+template <class P, int DIMS, int DH>
+static size_t bwd_lds_t(int N) {
+    constexpr int NW = BwdPick<P, DH>::NW, REGW = BwdPick<P, DH>::REGW;
+    typedef BwdCfg<P, DIMS, DH, NW> C;
+    const size_t es = sizeof(typename P::store_t);
+    size_t n = (size_t)C::MT * C::D_LD * es + (size_t)C::MT * (16 + 8 + 4);
+    n += ((size_t)C::MT * N + 15) / 16 * 16;
+    if (REGW) n += (size_t)DH * (2 * DH + C::PADE) * es;
+    return n;
+}
+template <class P, int DIMS>
+static size_t bwd_lds_d(int DH, int N) {
+    switch (DH) {
+        case 16: return bwd_lds_t<P, DIMS, 16>(N);
+        case 32: return bwd_lds_t<P, DIMS, 32>(N);
+        case 64: return bwd_lds_t<P, DIMS, 64>(N);
+        case 128: return bwd_lds_t<P, DIMS, 128>(N);
+        case 256: return bwd_lds_t<P, DIMS, 256>(N);
+    }
+    return (size_t)1 << 30;
+}
+size_t backward_lds(const Dims &d) {
+    if (d.prec == VMC_BF16) return d.dims == 1 ? bwd_lds_d<BF16, 1>(d.DH, d.N) : bwd_lds_d<BF16, 2>(d.DH, d.N);
+    return d.dims == 1 ? bwd_lds_d<F32, 1>(d.DH, d.N) : bwd_lds_d<F32, 2>(d.DH, d.N);
+}
+
 hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st) {
     BwdArgs a;
     a.d = b.d;
