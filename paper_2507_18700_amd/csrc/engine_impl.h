@@ -74,11 +74,29 @@ struct Eng {
     static constexpr int H_LD = KHB + PADE;                    // row stride of sH / sV
     static constexpr int X_LD = KS + PADE;                     // row stride of the indicator tile
     static constexpr int NLOG = 3;                             // head-sum buffers
+    // Register-resident weights (bfloat16, d_h <= 128): the one-hot inputs and
+    // gate biases enter the cell as the accumulators' start values, read from an
+    // FP32 table [gate][input class][unit] instead of an indicator k-step of
+    // MFMAs.  Input class = (x_hz + 1) + 3 (x_vt + 1), x = -1 when absent.
+    static constexpr bool XT = P::VEC == 8 && DH <= 128;
+    static constexpr int NXC = DIMS == 1 ? 3 : 9;              // input classes
+    static constexpr int NXG = DIMS == 1 ? 3 : 2;              // gates with inputs or a bias
+    static constexpr int XT_LD = DH + 4;                       // class stride: classes on distinct banks
     // static LDS of the kernel (bytes), for the host-side capacity check
     static constexpr size_t LDS =
-        sizeof(typename P::store_t) * ((size_t)2 * MT * H_LD + (DIMS == 2 ? 2 * MT * H_LD : 8) + 2 * MT * X_LD) +
-        4 * ((size_t)NLOG * WU * MT * 4 + 6 * DH) + 8 * MT + 16 * MT + 16;  // (+ the LDS constants of streamed weights)
+        sizeof(typename P::store_t) *
+            ((size_t)2 * MT * H_LD + (DIMS == 2 ? 2 * MT * H_LD : 8) + (XT ? 16 : 2 * MT * X_LD)) +
+        4 * ((size_t)NLOG * WU * MT * 4 + 6 * DH) + 8 * MT + 16 * MT + 16 +
+        (XT ? 4 * ((size_t)NXG * NXC * XT_LD + 2 * MT) : 16);  // (+ the LDS constants of streamed weights)
 };
+
+// Read-only tables written by earlier launches (position table, tile
+// schedule): through the constant address space, so that reads at uniform
+// indices become scalar loads.
+template <class T>
+__device__ inline const __attribute__((address_space(4))) T *kconst(const T *p) {
+    return (const __attribute__((address_space(4))) T *)p;
+}
 
 // Sums over the four 16-lane groups of two values at once: p ends up summed
 // in lanes 0-31 and q in lanes 32-63 (same bits within each half).  One
@@ -140,7 +158,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 
     __shared__ __align__(16) T sH[2][MT * H_LD];
     __shared__ __align__(16) T sV[DIMS == 2 ? 2 : 1][DIMS == 2 ? MT * H_LD : 8];
-    __shared__ __align__(16) T sX[2][MT * X_LD];
+    static_assert(C::XT == (bool)REGW, "input table goes with register-resident weights");
+    constexpr bool XT = C::XT;
+    __shared__ __align__(16) T sX[2][XT ? 8 : MT * X_LD];
+    __shared__ __align__(16) float sXt[XT ? C::NXG : 1][XT ? C::NXC : 1][XT ? C::XT_LD : 4];
+    __shared__ int sCmb[2][XT ? MT : 1];  // input class of each row, double-buffered like sX
     __shared__ __align__(16) float sLog[C::NLOG][C::WU][MT][4];
     __shared__ __align__(16) float sHw[2][DH];  // phase-head rows (complex amplitudes)
     // streamed weights (no REGW): the per-unit GLU biases and amplitude-head
@@ -208,13 +230,14 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     const float hc0 = a.hc[0], hc1 = a.hc[1], hc2 = a.hc[2], hc3 = a.hc[3];
 
     // REGW: cell and GLU weight fragments in registers for the whole launch
-    i32x4_t wreg[REGW ? 3 : 1][REGW ? NKS : 1][REGW ? UB : 1];
+    // (the hidden k-steps; the indicator columns come from the input table)
+    i32x4_t wreg[REGW ? 3 : 1][REGW ? NKS - 1 : 1][REGW ? UB : 1];
     uint4 wgl[REGW ? 2 : 1][REGW ? NKG : 1][REGW ? UB : 1];
     if (REGW) {
 #pragma unroll
         for (int g = 0; g < 3; g++)
 #pragma unroll
-            for (int ks = 0; ks < NKS; ks++)
+            for (int ks = 0; ks < NKS - 1; ks++)
 #pragma unroll
                 for (int ub = 0; ub < UB; ub++) {
                     const int n = g * DH + wu * C::UW + ub * 16 + l16;
@@ -235,14 +258,35 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     for (int e = tid; e < 2 * MT * H_LD; e += NT) (&sH[0][0])[e] = cvt<P>(0.f);
     if (DIMS == 2)
         for (int e = tid; e < 2 * MT * H_LD; e += NT) (&sV[0][0])[e] = cvt<P>(0.f);
-    for (int e = tid; e < 2 * MT * X_LD; e += NT) {
-        const int c = e % X_LD;
-        const bool bias_col = VEC == 8 ? (c == 8 || c == 9) : c == 4;
-        (&sX[0][0])[e] = cvt<P>(bias_col ? 1.f : 0.f);
-    }
+    if (!XT)
+        for (int e = tid; e < 2 * MT * X_LD; e += NT) {
+            const int c = e % X_LD;
+            const bool bias_col = VEC == 8 ? (c == 8 || c == 9) : c == 4;
+            (&sX[0][0])[e] = cvt<P>(bias_col ? 1.f : 0.f);
+        }
+    if (XT)
+        for (int e = tid; e < C::NXG * C::NXC * DH; e += NT) {
+            const int g = e / (C::NXC * DH), r = e - g * (C::NXC * DH), cls = r / DH, u = r - cls * DH;
+            const int xz = cls % 3 - 1, xv = cls / 3 - 1;
+            float v;
+            if (DIMS == 1) {
+                // gates u, r: bias + one-hot weight of x_{n-1}; gate m: its bias only
+                const float *e1 = a.E + (int64_t)(3 * g) * DH + u;
+                v = e1[0];
+                if (g < 2) v += xz == 0 ? e1[DH] : xz == 1 ? e1[2 * DH] : 0.f;
+            } else {
+                // gates c, u: bias + one-hot weights of the horizontal and vertical inputs
+                const float *e2 = a.E + (int64_t)(5 * g) * DH + u;
+                v = e2[0];
+                v += xz == 0 ? e2[DH] : xz == 1 ? e2[2 * DH] : 0.f;
+                v += xv == 0 ? e2[3 * DH] : xv == 1 ? e2[4 * DH] : 0.f;
+            }
+            sXt[XT ? g : 0][XT ? cls : 0][XT ? u : 0] = v;
+        }
 
     auto pos = [&](int qn) -> PosInfo __attribute__((always_inline)) {
-        const int4 t = postab[qn];
+        const auto *pt = kconst((const int *)postab) + 4 * qn;
+        const int4 t = make_int4(pt[0], pt[1], pt[2], pt[3]);
         PosInfo r;
         r.site = t.x & 0xFFFF;
         r.colw = DIMS == 2 && ((t.x >> 16) & 1);
@@ -294,17 +338,20 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             __syncthreads();
             if (tid == 0) sTile = atomicAdd(a.tile_counter, 1);
             __syncthreads();
-            const int t = sTile;
-            if (t >= a.tile_start[N]) break;
+            // uniform across the work-group: the position loop, its table reads
+            // and branches then run on the scalar unit
+            const int t = __builtin_amdgcn_readfirstlane(sTile);
+            const auto *ts = kconst(a.tile_start);
+            if (t >= ts[N]) break;
             int lo = 0, hi = N - 1;  // largest p with tile_start[p] <= t
             while (lo < hi) {
                 int mid = (lo + hi + 1) >> 1;
-                if (a.tile_start[mid] <= t) lo = mid;
+                if (ts[mid] <= t) lo = mid;
                 else hi = mid - 1;
             }
             p = lo;
-            e0 = (int64_t)(t - a.tile_start[p]) * MT;
-            nrow = (int)min((int64_t)MT, (int64_t)a.cnt[p] - e0);
+            e0 = (int64_t)(t - ts[p]) * MT;
+            nrow = (int)min((int64_t)MT, (int64_t)kconst(a.cnt)[p] - e0);
         } else {
             if (!first) break;
             e0 = (int64_t)blockIdx.x * MT;
@@ -433,9 +480,13 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             const int orow = lane;
             const int xz = pi.site_hz >= 0 ? sSig[orow * N + pi.site_hz] : -1;
             const int xv = pi.site_vt >= 0 ? sSig[orow * N + pi.site_vt] : -1;
-            const uint32_t one = VEC == 8 ? 0x3F803F80u : 0x3F800000u;
-            *(uint4 *)&sX[buf][orow * X_LD] = make_uint4(xz == 0 ? one : 0u, xz == 1 ? one : 0u,
-                                                         xv == 0 ? one : 0u, xv == 1 ? one : 0u);
+            if (XT) {
+                sCmb[buf][XT ? orow : 0] = (xz + 1) + 3 * (xv + 1);
+            } else {
+                const uint32_t one = VEC == 8 ? 0x3F803F80u : 0x3F800000u;
+                *(uint4 *)&sX[buf][orow * X_LD] = make_uint4(xz == 0 ? one : 0u, xz == 1 ? one : 0u,
+                                                             xv == 0 ? one : 0u, xv == 1 ? one : 0u);
+            }
         };
 
         // cell of position qc: A fragment of row block rb, k-step ks
@@ -580,14 +631,24 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                     }
                 };
                 auto cblock = [&](int rb, f32x4_t *acc) __attribute__((always_inline)) {
+                    // start values: bias and one-hot inputs of the row's input class
+                    const int cls = sCmb[qc & 1][XT ? wr * C::RW + rb * 16 + l16 : 0];
 #pragma unroll
-                    for (int c = 0; c < 3 * UB; c++) acc[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+                    for (int g = 0; g < 3; g++)
 #pragma unroll
-                    for (int ks = 0; ks < NKS; ks++) {
+                        for (int ub = 0; ub < UB; ub++) {
+                            if (g < C::NXG) {
+                                const float4 t = *(const float4 *)&sXt[XT ? g : 0][XT ? cls : 0][XT ? unit0(ub) : 0];
+                                acc[g * UB + ub] = f32x4_t{t.x, t.y, t.z, t.w};
+                            } else {
+                                acc[g * UB + ub] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+                            }
+                        }
+#pragma unroll
+                    for (int ks = 0; ks < NKS - 1; ks++) {
                         const int blk = ks / NKB;
-                        const bool is_x = ks == NKS - 1;
-                        if (!is_x && blk == 0 && !hz) continue;
-                        if (!is_x && blk == 1 && !vt) continue;
+                        if (blk == 0 && !hz) continue;
+                        if (blk == 1 && !vt) continue;
                         const uint4 af = a_frag(qc, vt_prev, rb, ks);
 #pragma unroll
                         for (int g = 0; g < 3; g++)
