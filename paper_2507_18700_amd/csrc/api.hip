@@ -226,6 +226,10 @@ static X *at(void *ws, size_t off) {
 
 static vmc_status hip_status(hipError_t e) { return e == hipSuccess ? VMC_OK : VMC_EDEVICE; }
 
+// every launch's LDS (static tiles plus the tile's configurations, rows x N
+// bytes) must fit one compute unit, for every tile choice
+static bool lds_fits(const Dims &d) { return engine_lds(d) <= kMaxLds && backward_lds(d) <= kMaxLds; }
+
 static vmc_status check_common(const vmc_model *m, const float *params, int64_t n, void *ws, size_t ws_bytes,
                                const vmc_ham *H, size_t *need) {
     if (!valid_model(m) || !params || n < 1 || !ws) return VMC_EINVAL;
@@ -233,9 +237,7 @@ static vmc_status check_common(const vmc_model *m, const float *params, int64_t 
     if (padded_dh(m->d_h) < 0) return VMC_EUNSUPPORTED;
     if (n >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
     Dims d = make_dims(m);
-    // every launch's LDS (static tiles plus the tile's configurations, rows x N
-    // bytes) must fit one compute unit, for every tile choice
-    if (engine_lds(d) > kMaxLds || backward_lds(d) > kMaxLds) return VMC_EUNSUPPORTED;
+    if (!lds_fits(d)) return VMC_EUNSUPPORTED;
     if (H && H->kind == VMC_HEISENBERG && n * bond_count(d.Lx, d.Ly) >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
     WsMap w = ws_map(d, H, n);
     if (need) *need = w.total;
@@ -290,6 +292,7 @@ vmc_status vmc_workspace_size(const vmc_model *m, const vmc_ham *H, int64_t ns, 
     if (padded_dh(m->d_h) < 0) return VMC_EUNSUPPORTED;
     if (H && H->kind != VMC_TFIM && H->kind != VMC_HEISENBERG) return VMC_EINVAL;
     Dims d = make_dims(m);
+    if (!lds_fits(d)) return VMC_EUNSUPPORTED;
     *bytes = ws_map(d, H, ns).total;
     return VMC_OK;
 }

@@ -156,3 +156,25 @@ def test_tuning_table(lib):
         assert lib.get_tuning(m) == {"row_tile": 64, "chain_wgs_per_cu": 1}
         lib.reset_tuning(m)
         lib.reset_tuning(m3)
+
+
+def test_lds_size_limits(lib):
+    """A model whose tiles do not fit the 160 KiB LDS of a compute unit is
+    refused as unsupported, by the workspace query and by every entry point,
+    before any device pointer is touched: bfloat16 d_h = 128 takes 2D lattices
+    up to 29x29, d_h = 256 up to 24x24."""
+    L = lib.lib()
+    out = ctypes.c_size_t(0)
+    for dh, ok in ((128, 29), (256, 24)):
+        m = lib.model(dims=2, Lx=ok, Ly=ok, d_h=dh, glu=True, precision=lib.VMC_BF16)
+        assert L.vmc_workspace_size(ctypes.byref(m), None, 10, ctypes.byref(out)) == 0
+        m = lib.model(dims=2, Lx=ok + 1, Ly=ok + 1, d_h=dh, glu=True, precision=lib.VMC_BF16)
+        assert L.vmc_workspace_size(ctypes.byref(m), None, 10, ctypes.byref(out)) == -2
+        fake = ctypes.c_void_p(0x100000)
+        ws = ctypes.c_void_p(0x200000)
+        assert L.rnn_logpsi(ctypes.byref(m), fake, 10, fake, fake, None, ws, 1 << 40, None) == -2
+        H = lib.ham(lib.VMC_TFIM, 1.0, 1.0)
+        assert L.local_energy(ctypes.byref(m), fake, ctypes.byref(H), 10, fake, fake, ws, 1 << 40, None) == -2
+    # 1D chains up to N = 1024 at every width
+    m = lib.model(dims=1, Lx=1024, d_h=256, glu=True, precision=lib.VMC_BF16)
+    assert L.vmc_workspace_size(ctypes.byref(m), None, 10, ctypes.byref(out)) == 0

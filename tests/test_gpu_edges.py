@@ -105,3 +105,45 @@ def test_many_samples_ragged():
     stats = st.cpu().numpy()
     assert np.isfinite(stats).all() and stats[3] == 0
     assert np.isfinite(g.cpu().numpy()).all()
+
+
+def test_largest_2d_lattice():
+    """2D 29x29, bfloat16, d_h = 128 with GLU: the largest square lattice whose
+    tiles fit the LDS at that width (30x30 is refused, see test_abi).  Sampling
+    from given uniforms and log psi against the oracle's bf16 emulation; the
+    local energy of one sample against its connected configurations through the
+    teacher-forced path, a few of them pinned to the oracle."""
+    torch = torch_gpu()
+    from oracle import oracle as O
+    from paper_2507_18700_amd import vmcrnn as V
+    L = 29
+    spec, gm, om = lib_and_oracle(2, L, L, 128, False, True, True)
+    N = spec.N
+    p = synth.xavier_params(spec, 12, bias_scale=0.1)
+    pd = torch.from_numpy(p).cuda()
+    ns = 6
+    uni = synth.uniforms(ns, N, 5)
+    cfg, lp, _ = V.rnn_sample(gm, pd, ns, uniforms=torch.from_numpy(uni).cuda())
+    torch.cuda.synchronize()
+    c = cfg.cpu().numpy()
+    lpg = lp.cpu().numpy().astype(np.float64)
+    p64 = p.astype(np.float64)
+    check_samples(O, om, p64, c, uni.astype(np.float64), L, L, 1e-3)
+    rlp, _ = O.logpsi(om, p64, c)
+    assert rel_max(lpg, rlp) < 2e-4
+    hx = 1.0
+    e = V.local_energy(gm, pd, V.ham(V.VMC_TFIM, 1.0, hx), cfg[:1].contiguous())
+    torch.cuda.synchronize()
+    eg = e.cpu().numpy()[0]
+    # TFIM: one connection per site (that spin flipped), coefficient -h
+    conn = np.repeat(c[:1], N, axis=0)
+    conn[np.arange(N), np.arange(N)] ^= 1
+    lpc, _ = V.rnn_logpsi(gm, pd, torch.from_numpy(conn).cuda())
+    torch.cuda.synchronize()
+    lpc = lpc.cpu().numpy().astype(np.float64)
+    s = (1 - 2 * c[0].astype(np.int64)).reshape(L, L)
+    diag = -((s[:, 1:] * s[:, :-1]).sum() + (s[1:, :] * s[:-1, :]).sum())
+    e_tf = diag - hx * np.sum(np.exp(0.5 * (lpc - lpg[0])))
+    assert abs(e_tf - eg[0]) / max(abs(e_tf), N) < 1e-5 and eg[1] == 0.0
+    olp, _ = O.logpsi(om, p64, conn[[0, N // 2, N - 1]])
+    assert rel_max(lpc[[0, N // 2, N - 1]], olp) < 2e-4
