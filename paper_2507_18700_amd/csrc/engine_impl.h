@@ -631,6 +631,8 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                     }
                 };
                 auto cblock = [&](int rb, f32x4_t *acc) __attribute__((always_inline)) {
+                    // scheduling hint: interleave the operand reads with the MFMAs
+                    __builtin_amdgcn_iglp_opt(0);
                     // start values: bias and one-hot inputs of the row's input class
                     const int cls = sCmb[qc & 1][XT ? wr * C::RW + rb * 16 + l16 : 0];
 #pragma unroll
