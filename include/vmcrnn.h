@@ -50,11 +50,16 @@ typedef enum {
                               or a kernel's LDS (its tile's configurations, tile rows
                               x N bytes, plus its static tiles) above 160 KiB */
     VMC_ENOSPACE = -3,     /* workspace smaller than vmc_workspace_size() */
-    VMC_EDEVICE = -4       /* a HIP call or kernel launch failed */
+    VMC_EDEVICE = -4,      /* a HIP call or kernel launch failed */
+    VMC_ENONFINITE = -5    /* a non-finite value where a finite one is required: a
+                              Hamiltonian coupling, field or exponent, the noise of
+                              grow_hidden, an Adam setting, or (vmc_check_finite) an
+                              entry of a device array */
 } vmc_status;
 
 enum { VMC_FP32 = 0, VMC_BF16 = 1 };      /* GEMM operand precision */
-enum { VMC_TFIM = 0, VMC_HEISENBERG = 1 }; /* Hamiltonians, Eqs. (6), (7) */
+/* Hamiltonians: Eqs. (6), (7), (8), (9) */
+enum { VMC_TFIM = 0, VMC_HEISENBERG = 1, VMC_LRTFIM = 2, VMC_CLUSTER = 3 };
 
 /* Wave-function descriptor.  N = Lx*Ly sites (1D: Ly = 1).  d_h in [1,256];
  * d_model = d_h.  precision: VMC_FP32 = FP32 MFMA operands, VMC_BF16 =
@@ -74,11 +79,20 @@ typedef struct {
  *  VMC_TFIM       H = -J sum_<ab> Z_a Z_b - h sum_k X_k                (Eq. 6)
  *  VMC_HEISENBERG H = J/4 sum_<ab> (X_a X_b + Y_a Y_b + Z_a Z_b)       (Eq. 7)
  *                 with marshall != 0, the Marshall-sign rotated form whose
- *                 off-diagonal elements are all negative (Sec. III B).     */
+ *                 off-diagonal elements are all negative (Sec. III B).
+ *  VMC_LRTFIM     H = -J sum_{i<j} Z_i Z_j / |i-j|^alpha - h sum_k X_k
+ *                 (Eq. 8, long-range TFIM; 1D only)
+ *  VMC_CLUSTER    H = -J [ sum_{k=2}^{n-2} X_{k-1} Z_k X_{k+1}
+ *                         + Z_1 X_2 + X_{n-1} X_n + X_{n-2} Z_{n-1} Z_n ]
+ *                 (Eq. 9, 1D cluster state with the boundary terms as the
+ *                 paper writes them, sites 1..n; n >= 3; 1D only).
+ * Every coupling must be finite (VMC_ENONFINITE otherwise); alpha is read by
+ * VMC_LRTFIM only and must be >= 0. */
 typedef struct {
     int32_t kind;
     int32_t marshall;
     double J, h;
+    double alpha;
 } vmc_ham;
 
 /* Number of float parameters of the flat vector described above; -1 if the
@@ -87,7 +101,9 @@ int64_t vmc_param_count(const vmc_model *m);
 
 /* Workspace bytes needed by any call below with this model, Hamiltonian
  * (may be NULL when local_energy is not used) and up to `ns` samples or
- * configurations per call. */
+ * configurations per call.  Checks the Hamiltonian like the calls do
+ * (VMC_ENONFINITE for a non-finite coupling, VMC_EUNSUPPORTED for a 1D-only
+ * kind on a 2D lattice). */
 vmc_status vmc_workspace_size(const vmc_model *m, const vmc_ham *H, int64_t ns, size_t *bytes);
 
 /* Perfect autoregressive sampling (Sec. II A, Eq. 1): for each sample s and
@@ -148,11 +164,53 @@ vmc_status rnn_logpsi_grad(const vmc_model *m, const float *params, int64_t nc, 
  * the hidden states, conditionals and activations that the local energy and
  * the backward sweep need).  Outputs equal those of the three separate calls
  * with the same arguments.  uniforms may be NULL (Philox as in rnn_sample);
- * phase may be NULL. */
+ * phase may be NULL.
+ *  counter_dev: NULL, or a device uint64 that replaces `counter`: the sampler
+ *            reads the Philox counter from it when it runs, and the step's
+ *            last kernel adds 1 to it, so that the replays of a captured HIP
+ *            graph of this call draw fresh uniforms, step after step, equal
+ *            to those of eager calls with counter = k, k+1, ...
+ * Non-finite parameters are not detected here (that would need a host
+ * synchronisation): they make the outputs non-finite, stats[3] = ns; see
+ * vmc_check_finite. */
 vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns,
-                    uint64_t seed, uint64_t counter, const float *uniforms, uint8_t *configs,
-                    float *logp, float *phase, double *eloc, double *grad, double *stats,
-                    void *ws, size_t ws_bytes, void *stream);
+                    uint64_t seed, uint64_t counter, uint64_t *counter_dev, const float *uniforms,
+                    uint8_t *configs, float *logp, float *phase, double *eloc, double *grad,
+                    double *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* Adam update (Kingma & Ba, ICLR 2015), the optimiser of every benchmark of
+ * the paper (App. B), of n float32 parameters from an FP64 gradient:
+ *    t = *t_dev + 1,  lr = lr(t - 1),
+ *    m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *    p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
+ * then *t_dev = t (a trailing one-thread kernel, so the update reads the old
+ * value).  m and v are float32 [n], carried through grow_hidden when the
+ * hidden width grows (App. B).  t_dev is a device int64 (updates done so
+ * far), so a captured HIP graph keeps counting on replay.  The learning
+ * rate at update index k = t - 1 follows the schedules of Table III:
+ *    lr(k) = (k < t_switch ? lr0 : lr1) / (1 + max(0, k - t_decay) / tau)
+ * with tau = 0 meaning no decay (constant, two-stage, inverse-time).
+ * Every setting must be finite (VMC_ENONFINITE), lr >= 0, 0 <= b1, b2 < 1,
+ * eps > 0, tau >= 0 (VMC_EINVAL). */
+typedef struct {
+    double lr0, lr1;
+    int64_t t_switch;
+    int64_t t_decay;
+    double tau;
+    double beta1, beta2, eps;
+} vmc_adam_cfg;
+
+vmc_status vmc_adam(int64_t n, float *params, const double *grad, float *m, float *v, int64_t *t_dev,
+                    const vmc_adam_cfg *cfg, void *stream);
+
+/* Synchronous check that the n float32 entries of the device array x are all
+ * finite: counts the non-finite ones on `stream` (into the first 256 bytes of
+ * the workspace, ws_bytes >= 256), waits for the stream, and returns
+ * VMC_ENONFINITE if the count is not zero (*count, if not NULL, receives
+ * it).  Meant before a run or after a failed step, not inside a captured
+ * graph. */
+vmc_status vmc_check_finite(const float *x, int64_t n, int64_t *count, void *ws, size_t ws_bytes,
+                            void *stream);
 
 /* Adaptive growth of the hidden width (Sec. II B, Fig. 2(b); App. B):
  * copies every parameter of `from` into the model with d_h = new_dh

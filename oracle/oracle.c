@@ -54,9 +54,11 @@ typedef struct {
 } ora_model;
 
 typedef struct {
-    int32_t kind;       /* 0 = transverse-field Ising, 1 = Heisenberg */
+    int32_t kind;       /* 0 = transverse-field Ising, 1 = Heisenberg,
+                           2 = long-range transverse-field Ising, 3 = cluster */
     int32_t marshall;   /* Heisenberg: rotate by the Marshall sign */
     double J, h;        /* coupling, transverse field */
+    double alpha;       /* long-range exponent (kind 2) */
 } ora_ham;
 
 typedef struct {
@@ -488,6 +490,34 @@ int32_t ora_bond_count(const ora_model *m)
 }
 
 /*
+ * The 1D cluster Hamiltonian of Eq. (9), sites 1..n as the paper numbers them:
+ *   H = -sum_{k=2}^{n-2} X_{k-1} Z_k X_{k+1} - Z_1 X_2 - X_{n-1} X_n
+ *       - X_{n-2} Z_{n-1} Z_n,
+ * stored as Pauli strings: for term t, the 0-indexed sites acted on by X
+ * (xs, nx of them) and by Z (zs, nz).  Returns the number of terms.
+ */
+typedef struct {
+    int nx, nz;
+    int xs[2], zs[2];
+} pauli_term;
+
+static int cluster_terms(int n, pauli_term *T)
+{
+    int nt = 0;
+    for (int k = 2; k <= n - 2; k++) { /* X_{k-1} Z_k X_{k+1} */
+        pauli_term t = {2, 1, {k - 2, k}, {k - 1, 0}};
+        T[nt++] = t;
+    }
+    pauli_term a = {1, 1, {1, 0}, {0, 0}};                 /* Z_1 X_2 */
+    pauli_term b = {2, 0, {n - 2, n - 1}, {0, 0}};         /* X_{n-1} X_n */
+    pauli_term c = {1, 2, {n - 3, 0}, {n - 2, n - 1}};     /* X_{n-2} Z_{n-1} Z_n */
+    T[nt++] = a;
+    T[nt++] = b;
+    T[nt++] = c;
+    return nt;
+}
+
+/*
  * Local energy E_loc(sigma) = sum_sigma' H_{sigma,sigma'} psi(sigma')/psi(sigma)
  * with every connected configuration sigma' re-evaluated in full.
  *  Transverse-field Ising (Eq. (6); on the square lattice for 2D):
@@ -496,6 +526,12 @@ int32_t ora_bond_count(const ora_model *m)
  *    E_loc = J/4 sum_<ab> s_a s_b + sum_{<ab>: s_a != s_b} Jx psi(sigma^(ab))/psi(sigma)
  *    with Jx = +J/2, or -J/2 after the Marshall-sign rotation, which makes
  *    every off-diagonal element negative (Sec. III B).
+ *  Long-range transverse-field Ising (Eq. (8), chain):
+ *    E_loc = -J sum_{i<j} s_i s_j / |i-j|^alpha - h sum_k psi(sigma^(k))/psi(sigma)
+ *  Cluster state (Eq. (9), chain; scaled by J): every term is a Pauli string
+ *    of X and Z on distinct sites, so <sigma|term|sigma'> = prod_Z s_z with
+ *    sigma' = sigma flipped on the X sites, and
+ *    E_loc = -J sum_terms (prod_Z s_z) psi(sigma')/psi(sigma).
  * eloc[2s], eloc[2s+1] = real and imaginary part.
  */
 void ora_local_energy(const ora_model *m, const double *P, const ora_ham *H, int64_t ns,
@@ -518,7 +554,37 @@ void ora_local_energy(const ora_model *m, const double *P, const ora_ham *H, int
             double sa = 1.0 - 2.0 * c0[ba[b]], sb = 1.0 - 2.0 * c0[bb[b]];
             diag += sa * sb;
         }
-        if (H->kind == 0) {
+        if (H->kind == 2) {
+            diag = 0.0;
+            for (int i = 0; i < N; i++)
+                for (int j = i + 1; j < N; j++) {
+                    double si = 1.0 - 2.0 * c0[i], sj = 1.0 - 2.0 * c0[j];
+                    diag -= H->J * si * sj / pow((double)(j - i), H->alpha);
+                }
+            for (int k = 0; k < N; k++) {
+                memcpy(c1, c0, N);
+                c1[k] ^= 1;
+                forward_one(m, &L, P, c1, NULL, &lp1, &ph1, NULL, NULL, NULL);
+                double mag = exp(0.5 * (lp1 - lp0));
+                ore += -H->h * mag * cos(ph1 - ph0);
+                oim += -H->h * mag * sin(ph1 - ph0);
+            }
+        } else if (H->kind == 3) {
+            pauli_term *T = malloc((size_t)(N + 3) * sizeof(pauli_term));
+            int nt = cluster_terms(N, T);
+            diag = 0.0;
+            for (int t = 0; t < nt; t++) {
+                double coef = -H->J;
+                for (int z = 0; z < T[t].nz; z++) coef *= 1.0 - 2.0 * c0[T[t].zs[z]];
+                memcpy(c1, c0, N);
+                for (int x = 0; x < T[t].nx; x++) c1[T[t].xs[x]] ^= 1;
+                forward_one(m, &L, P, c1, NULL, &lp1, &ph1, NULL, NULL, NULL);
+                double mag = exp(0.5 * (lp1 - lp0));
+                ore += coef * mag * cos(ph1 - ph0);
+                oim += coef * mag * sin(ph1 - ph0);
+            }
+            free(T);
+        } else if (H->kind == 0) {
             diag *= -H->J;
             for (int k = 0; k < N; k++) {
                 memcpy(c1, c0, N);
@@ -895,6 +961,24 @@ void ora_grow_hidden(const ora_model *from, const double *p0, int32_t new_dh, ui
         }
     }
 #undef COPY
+}
+
+/* ------------------------------------------------------------------ Adam */
+
+/* One Adam update (Kingma & Ba, ICLR 2015; the optimiser of App. B) at step
+ * t >= 1 with learning rate lr:
+ *   m = b1 m + (1-b1) g,  v = b2 v + (1-b2) g^2,
+ *   p = p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+void ora_adam(int64_t n, double *p, const double *g, double *m, double *v, int64_t t, double lr,
+              double b1, double b2, double eps)
+{
+    for (int64_t i = 0; i < n; i++) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        double mh = m[i] / (1.0 - pow(b1, (double)t));
+        double vh = v[i] / (1.0 - pow(b2, (double)t));
+        p[i] -= lr * mh / (sqrt(vh) + eps);
+    }
 }
 
 int32_t ora_num_threads(void)

@@ -36,10 +36,10 @@ class Model(ctypes.Structure):
 
 class Ham(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("marshall", ctypes.c_int32),
-                ("J", ctypes.c_double), ("h", ctypes.c_double)]
+                ("J", ctypes.c_double), ("h", ctypes.c_double), ("alpha", ctypes.c_double)]
 
 
-TFIM, HEISENBERG = 0, 1
+TFIM, HEISENBERG, LRTFIM, CLUSTER = 0, 1, 2, 3
 
 _lib = None
 
@@ -69,6 +69,7 @@ def lib():
         L.ora_num_threads.restype = ctypes.c_int32
         L.ora_round_bf16.restype = d
         L.ora_round_bf16.argtypes = [d]
+        L.ora_adam.argtypes = [i64, P(d), P(d), P(d), P(d), i64, d, d, d, d]
         _lib = L
     return _lib
 
@@ -91,8 +92,8 @@ def model(dims=1, Lx=4, Ly=1, d_h=4, is_complex=False, glu=False, bf16=False):
     return Model(dims, Lx, Ly if dims == 2 else 1, d_h, int(is_complex), int(glu), int(bf16))
 
 
-def ham(kind=TFIM, J=1.0, h=1.0, marshall=False):
-    return Ham(kind, int(marshall), J, h)
+def ham(kind=TFIM, J=1.0, h=1.0, marshall=False, alpha=0.0):
+    return Ham(kind, int(marshall), J, h, alpha)
 
 
 def n_sites(m):
@@ -207,6 +208,13 @@ def grow_hidden(m, params, new_dh, seed, noise_std, m_mom=None, v_mom=None):
     if m_mom is not None or v_mom is not None:
         return p1, m1, v1
     return p1
+
+
+def adam(params, grad, m_mom, v_mom, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update at step t >= 1 on float64 copies; returns (p, m, v)."""
+    p, g, m1, v1 = _f64(params).copy(), _f64(grad), _f64(m_mom).copy(), _f64(v_mom).copy()
+    lib().ora_adam(p.size, _p(p), _p(g), _p(m1), _p(v1), int(t), float(lr), float(beta1), float(beta2), float(eps))
+    return p, m1, v1
 
 
 def num_threads():

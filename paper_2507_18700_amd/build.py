@@ -24,6 +24,7 @@ SOURCES = [
     "forward.hip",
     "grad.hip",
     "grow.hip",
+    "optim.hip",
 ]
 ARCH = "gfx950"
 

@@ -2,6 +2,8 @@
 // workspace layout and the launch sequence of each call.
 #include <string.h>
 
+#include <cmath>
+
 #include <array>
 #include <map>
 #include <mutex>
@@ -35,6 +37,10 @@ int64_t grad_nsp(int64_t ns);
 hipError_t launch_grow(const vmc_model &from, const float *p0, int new_dh, uint64_t seed, double noise,
                        float *p1, const float *m0, const float *v0, float *m1, float *v1,
                        int64_t n_to, hipStream_t st);
+hipError_t launch_bump(uint64_t *counter, hipStream_t st);
+hipError_t launch_adam(int64_t n, float *p, const double *g, float *m, float *v, int64_t *t_dev,
+                       const vmc_adam_cfg &c, hipStream_t st);
+hipError_t launch_count_nonfinite(const float *x, int64_t n, unsigned long long *count, hipStream_t st);
 
 static const int kMaxN = 1024;
 static const size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
@@ -49,6 +55,27 @@ static bool valid_model(const vmc_model *m) {
     if ((m->is_complex != 0 && m->is_complex != 1) || (m->glu != 0 && m->glu != 1)) return false;
     return true;
 }
+
+// The Hamiltonian descriptor against the model: known kind, finite
+// couplings, the 1D-only kinds on a chain.
+static vmc_status check_ham(const vmc_model *m, const vmc_ham *H) {
+    if (!H) return VMC_EINVAL;
+    if (H->kind != VMC_TFIM && H->kind != VMC_HEISENBERG && H->kind != VMC_LRTFIM && H->kind != VMC_CLUSTER)
+        return VMC_EINVAL;
+    if (!std::isfinite(H->J) || !std::isfinite(H->h)) return VMC_ENONFINITE;
+    if (H->kind == VMC_LRTFIM) {
+        if (!std::isfinite(H->alpha)) return VMC_ENONFINITE;
+        if (H->alpha < 0.0) return VMC_EINVAL;
+    }
+    if ((H->kind == VMC_LRTFIM || H->kind == VMC_CLUSTER) && m->dims != 1) return VMC_EUNSUPPORTED;
+    if (H->kind == VMC_CLUSTER && m->Lx < 3) return VMC_EINVAL;
+    return VMC_OK;
+}
+
+// connection kind of the chain engine and the schedule: one flip per
+// position (TFIM, LR-TFIM) or a connection list (Heisenberg, cluster)
+static int engine_kind(const vmc_ham *H) { return H->kind == VMC_LRTFIM ? VMC_TFIM : H->kind; }
+static bool list_kind(const vmc_ham *H) { return H && (H->kind == VMC_HEISENBERG || H->kind == VMC_CLUSTER); }
 
 static int padded_dh(int d) {
     static const int sizes[] = {16, 32, 64, 128, 256};
@@ -174,14 +201,14 @@ static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
     w.lpc = put((size_t)ns * d.N * 2 * 4);
     w.phc = put((size_t)ns * d.N * 2 * 4);
     w.pre = put((size_t)ns * d.N * 16);
-    const int nb = bond_count(d.Lx, d.Ly);
-    w.NC = (H && H->kind == VMC_HEISENBERG) ? nb : d.N;
+    const int nb = list_kind(H) ? conn_count(H->kind, d.Lx, d.Ly) : 0;
+    w.NC = list_kind(H) ? nb : d.N;
     w.dsuf = put((size_t)ns * w.NC * 16);
     w.cnt = put((size_t)(d.N + 1) * 4);
     w.list_off = put((size_t)(d.N + 1) * 4);
     w.tile_start = put((size_t)(d.N + 1) * 4);
     w.tile_counter = put(4);
-    w.list = put((H && H->kind == VMC_HEISENBERG) ? (size_t)ns * nb * 4 : 4);
+    w.list = put(list_kind(H) ? (size_t)ns * nb * 4 : 4);
     // the row launches cover every column of the transposed activation
     // arrays (nsp >= ns samples), so that the rows past ns hold zeros
     const int64_t nsp = grad_nsp(ns);
@@ -232,13 +259,18 @@ static bool lds_fits(const Dims &d) { return engine_lds(d) <= kMaxLds && backwar
 
 static vmc_status check_common(const vmc_model *m, const float *params, int64_t n, void *ws, size_t ws_bytes,
                                const vmc_ham *H, size_t *need) {
-    if (!valid_model(m) || !params || n < 1 || !ws) return VMC_EINVAL;
+    if (!valid_model(m)) return VMC_EINVAL;
+    if (H) {
+        const vmc_status hs = check_ham(m, H);
+        if (hs != VMC_OK) return hs;
+    }
+    if (!params || n < 1 || !ws) return VMC_EINVAL;
     if (((uintptr_t)ws & 255) != 0) return VMC_EINVAL;
     if (padded_dh(m->d_h) < 0) return VMC_EUNSUPPORTED;
     if (n >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
     Dims d = make_dims(m);
     if (!lds_fits(d)) return VMC_EUNSUPPORTED;
-    if (H && H->kind == VMC_HEISENBERG && n * bond_count(d.Lx, d.Ly) >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
+    if (list_kind(H) && n * conn_count(H->kind, d.Lx, d.Ly) >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
     WsMap w = ws_map(d, H, n);
     if (need) *need = w.total;
     if (ws_bytes < w.total) return VMC_ENOSPACE;
@@ -289,8 +321,11 @@ int64_t vmc_param_count(const vmc_model *m) {
 
 vmc_status vmc_workspace_size(const vmc_model *m, const vmc_ham *H, int64_t ns, size_t *bytes) {
     if (!valid_model(m) || ns < 1 || !bytes) return VMC_EINVAL;
+    if (H) {
+        const vmc_status hs = check_ham(m, H);
+        if (hs != VMC_OK) return hs;
+    }
     if (padded_dh(m->d_h) < 0) return VMC_EUNSUPPORTED;
-    if (H && H->kind != VMC_TFIM && H->kind != VMC_HEISENBERG) return VMC_EINVAL;
     Dims d = make_dims(m);
     if (!lds_fits(d)) return VMC_EUNSUPPORTED;
     *bytes = ws_map(d, H, ns).total;
@@ -353,12 +388,13 @@ static vmc_status eloc_from_cache(const Dims &d, const WsMap &w, void *ws, const
     a.lpc = at<float>(ws, w.lpc);
     a.phc = at<float>(ws, w.phc);
     a.pre = at<double2>(ws, w.pre);
-    hipError_t e = launch_sched(H->kind, d.Lx, d.Ly, ns, configs, at<int>(ws, w.cnt), at<int>(ws, w.list_off),
+    const int ek = engine_kind(H);
+    hipError_t e = launch_sched(ek, d.Lx, d.Ly, ns, configs, at<int>(ws, w.cnt), at<int>(ws, w.list_off),
                                 at<int>(ws, w.list), at<int>(ws, w.tile_start), at<int>(ws, w.tile_counter),
                                 chain_tile_rows(d), st);
     if (e != hipSuccess) return VMC_EDEVICE;
-    a.ham_kind = H->kind;
-    a.nbond = bond_count(d.Lx, d.Ly);
+    a.ham_kind = ek;
+    a.nbond = ek == VMC_TFIM ? 0 : conn_count(ek, d.Lx, d.Ly);
     a.cnt = at<int>(ws, w.cnt);
     a.tile_start = at<int>(ws, w.tile_start);
     a.list_off = at<int>(ws, w.list_off);
@@ -413,7 +449,7 @@ static vmc_status grad_from_cache(const Dims &d, const WsMap &w, void *ws, int64
 
 vmc_status local_energy(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns,
                         const uint8_t *configs, double *eloc, void *ws, size_t ws_bytes, void *stream) {
-    if (!H || (H->kind != VMC_TFIM && H->kind != VMC_HEISENBERG)) return VMC_EINVAL;
+    if (!H) return VMC_EINVAL;
     vmc_status s = check_common(m, params, ns, ws, ws_bytes, H, NULL);
     if (s != VMC_OK) return s;
     if (!configs || !eloc) return VMC_EINVAL;
@@ -485,9 +521,10 @@ vmc_status rnn_logpsi_grad(const vmc_model *m, const float *params, int64_t nc, 
 }
 
 vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns, uint64_t seed,
-                    uint64_t counter, const float *uniforms, uint8_t *configs, float *logp, float *phase,
-                    double *eloc, double *grad, double *stats, void *ws, size_t ws_bytes, void *stream) {
-    if (!H || (H->kind != VMC_TFIM && H->kind != VMC_HEISENBERG)) return VMC_EINVAL;
+                    uint64_t counter, uint64_t *counter_dev, const float *uniforms, uint8_t *configs, float *logp,
+                    float *phase, double *eloc, double *grad, double *stats, void *ws, size_t ws_bytes,
+                    void *stream) {
+    if (!H) return VMC_EINVAL;
     vmc_status s = check_common(m, params, ns, ws, ws_bytes, H, NULL);
     if (s != VMC_OK) return s;
     if (!configs || !logp || !eloc || !grad) return VMC_EINVAL;
@@ -501,6 +538,7 @@ vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, i
     a.uniforms = uniforms;
     a.seed = seed;
     a.counter = counter;
+    a.counter_dev = counter_dev;
     a.cfg_out = configs;
     a.cfg_in = configs;
     a.logp = logp;
@@ -522,7 +560,31 @@ vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, i
     if (e != hipSuccess) return VMC_EDEVICE;
     s = eloc_from_cache(d, w, ws, H, ns, configs, eloc, st);
     if (s != VMC_OK) return s;
-    return grad_from_cache(d, w, ws, ns, configs, eloc, NULL, grad, stats, st);
+    s = grad_from_cache(d, w, ws, ns, configs, eloc, NULL, grad, stats, st);
+    if (s != VMC_OK || !counter_dev) return s;
+    return hip_status(launch_bump(counter_dev, st));
+}
+
+vmc_status vmc_adam(int64_t n, float *params, const double *grad, float *m, float *v, int64_t *t_dev,
+                    const vmc_adam_cfg *cfg, void *stream) {
+    if (n < 1 || !params || !grad || !m || !v || !t_dev || !cfg) return VMC_EINVAL;
+    const double vals[] = {cfg->lr0, cfg->lr1, cfg->tau, cfg->beta1, cfg->beta2, cfg->eps};
+    for (double x : vals)
+        if (!std::isfinite(x)) return VMC_ENONFINITE;
+    if (cfg->lr0 < 0.0 || cfg->lr1 < 0.0 || cfg->tau < 0.0 || !(cfg->eps > 0.0)) return VMC_EINVAL;
+    if (cfg->beta1 < 0.0 || cfg->beta1 >= 1.0 || cfg->beta2 < 0.0 || cfg->beta2 >= 1.0) return VMC_EINVAL;
+    return hip_status(launch_adam(n, params, grad, m, v, t_dev, *cfg, (hipStream_t)stream));
+}
+
+vmc_status vmc_check_finite(const float *x, int64_t n, int64_t *count, void *ws, size_t ws_bytes, void *stream) {
+    if (!x || n < 1 || !ws || ws_bytes < 256 || ((uintptr_t)ws & 255) != 0) return VMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long *dc = (unsigned long long *)ws, hc = 0;
+    if (launch_count_nonfinite(x, n, dc, st) != hipSuccess) return VMC_EDEVICE;
+    if (hipMemcpyAsync(&hc, dc, sizeof(hc), hipMemcpyDeviceToHost, st) != hipSuccess) return VMC_EDEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return VMC_EDEVICE;
+    if (count) *count = (int64_t)hc;
+    return hc ? VMC_ENONFINITE : VMC_OK;
 }
 
 vmc_status grow_hidden(const vmc_model *from, const float *p_from, int32_t new_dh, uint64_t seed, double noise_std,
@@ -530,7 +592,8 @@ vmc_status grow_hidden(const vmc_model *from, const float *p_from, int32_t new_d
                        void *stream) {
     if (!valid_model(from) || !p_from || !p_to) return VMC_EINVAL;
     if (new_dh < from->d_h) return VMC_EINVAL;
-    if (!(noise_std >= 0.0)) return VMC_EINVAL;
+    if (!std::isfinite(noise_std)) return VMC_ENONFINITE;
+    if (noise_std < 0.0) return VMC_EINVAL;
     int nmom = (m_from != NULL) + (v_from != NULL) + (m_to != NULL) + (v_to != NULL);
     if (nmom != 0 && nmom != 4) return VMC_EINVAL;
     vmc_model to = *from;
@@ -617,7 +680,7 @@ vmc_status vmc_autotune_step(const vmc_model *m, const float *params, const vmc_
                              double *eloc, double *grad, double *stats, void *ws, size_t ws_bytes, void *stream,
                              int32_t reps, vmc_tuning *best) {
     if (reps < 1 || reps > 100) return VMC_EINVAL;
-    if (!H || (H->kind != VMC_TFIM && H->kind != VMC_HEISENBERG)) return VMC_EINVAL;
+    if (!H) return VMC_EINVAL;
     vmc_status s = check_common(m, params, ns, ws, ws_bytes, H, NULL);
     if (s != VMC_OK) return s;
     if (!configs || !logp || !eloc || !grad) return VMC_EINVAL;
@@ -635,8 +698,8 @@ vmc_status vmc_autotune_step(const vmc_model *m, const float *params, const vmc_
         float bestms = 1e30f;
         for (int i = 0; i < reps; i++) {
             if (hipEventRecord(ev[0], st) != hipSuccess) return VMC_EDEVICE;
-            r = vmc_step(m, params, H, ns, seed, counter, uniforms, configs, logp, phase, eloc, grad, stats, ws,
-                         ws_bytes, stream);
+            r = vmc_step(m, params, H, ns, seed, counter, NULL, uniforms, configs, logp, phase, eloc, grad, stats,
+                         ws, ws_bytes, stream);
             if (r != VMC_OK) return r;
             float t_ms = 0.f;
             if (hipEventRecord(ev[1], st) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
@@ -692,6 +755,7 @@ const char *vmc_status_str(vmc_status s) {
         case VMC_EUNSUPPORTED: return "unsupported configuration";
         case VMC_ENOSPACE: return "workspace too small";
         case VMC_EDEVICE: return "device error";
+        case VMC_ENONFINITE: return "non-finite value";
     }
     return "unknown status";
 }

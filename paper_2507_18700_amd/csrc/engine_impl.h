@@ -228,6 +228,8 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     };
     for (int e = tid; e < C::NLOG * C::WU * MT * 4; e += NT) (&sLog[0][0][0][0])[e] = 0.f;
     const float hc0 = a.hc[0], hc1 = a.hc[1], hc2 = a.hc[2], hc3 = a.hc[3];
+    // Philox counter of the sampling decisions: given, or read once from device memory
+    const uint64_t ctr = (!TF && a.counter_dev) ? *kconst(a.counter_dev) : a.counter;
 
     // REGW: cell and GLU weight fragments in registers for the whole launch
     // (the hidden k-steps; the indicator columns come from the input table)
@@ -374,7 +376,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                     const int conn = a.list[a.list_off[p] + ent];
                     my_s = conn / a.nbond;
                     cidx = conn - my_s * a.nbond;
-                    bond_sites(cidx, Lx, Ly, f1, f2);
+                    conn_sites(a.ham_kind, cidx, Lx, Ly, f1, f2);
                 }
             }
             sRow[tid] = my_s;
@@ -800,8 +802,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
                 if (a.uniforms) {
                     uni = a.uniforms[(int64_t)s * N + qf];
                 } else {
-                    uint32_t c4[4] = {(uint32_t)(qf >> 2), (uint32_t)s, (uint32_t)a.counter,
-                                      (uint32_t)(a.counter >> 32)};
+                    uint32_t c4[4] = {(uint32_t)(qf >> 2), (uint32_t)s, (uint32_t)ctr, (uint32_t)(ctr >> 32)};
                     philox4x32_10(c4, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
                     const uint32_t wsel =
                         (qf & 3) == 0 ? c4[0] : (qf & 3) == 1 ? c4[1] : (qf & 3) == 2 ? c4[2] : c4[3];

@@ -188,13 +188,24 @@ __global__ void build_postab(Dims d, int4 *tab) {
 
 // --------------------------------------------------------- chain schedule
 
+// first changed order position of connection c (list kinds)
+__device__ inline int conn_first_pos(int kind, int c, int Lx, int Ly) {
+    int sa, sc;
+    conn_sites(kind, c, Lx, Ly, sa, sc);
+    const int pa = site_pos(sa, Lx);
+    if (sc < 0) return pa;
+    const int pc = site_pos(sc, Lx);
+    return pa < pc ? pa : pc;
+}
+
 // Per first-changed position p: capacity offsets of the connection list
-// (Heisenberg) or the row counts (TFIM: every sample, p < N-1), the zeroed
-// counters, and the tile counter.
+// (list kinds: Heisenberg bonds, cluster terms) or the row counts (one flip
+// per position: every sample, p < N-1), the zeroed counters, and the tile
+// counter.
 __global__ __launch_bounds__(1024) void sched_prep(int ham_kind, int Lx, int Ly, int64_t ns, int *cnt,
                                                    int *list_off, int *tile_counter) {
-    // one work-group: bonds counted per first changed position in LDS, then
-    // one thread lays out the list offsets (N <= 1024)
+    // one work-group: connections counted per first changed position in LDS,
+    // then one thread lays out the list offsets (N <= 1024)
     __shared__ int kb[1025];
     const int N = Lx * Ly, tid = threadIdx.x;
     if (tid == 0) *tile_counter = 0;
@@ -204,13 +215,8 @@ __global__ __launch_bounds__(1024) void sched_prep(int ham_kind, int Lx, int Ly,
     }
     for (int p = tid; p < N; p += blockDim.x) kb[p] = 0;
     __syncthreads();
-    const int nb = bond_count(Lx, Ly);
-    for (int b = tid; b < nb; b += blockDim.x) {
-        int sa, sc;
-        bond_sites(b, Lx, Ly, sa, sc);
-        const int pa = site_pos(sa, Lx), pc = site_pos(sc, Lx);
-        atomicAdd(&kb[pa < pc ? pa : pc], 1);
-    }
+    const int nb = conn_count(ham_kind, Lx, Ly);
+    for (int b = tid; b < nb; b += blockDim.x) atomicAdd(&kb[conn_first_pos(ham_kind, b, Lx, Ly)], 1);
     __syncthreads();
     if (tid == 0) {
         int64_t off = 0;
@@ -223,20 +229,23 @@ __global__ __launch_bounds__(1024) void sched_prep(int ham_kind, int Lx, int Ly,
     for (int p = tid; p < N; p += blockDim.x) cnt[p] = 0;
 }
 
-// Heisenberg: every anti-aligned bond of every sample is one connection,
-// filed under its first changed order position.
-__global__ void heis_list(const uint8_t *cfg, int64_t ns, int Lx, int Ly, int *cnt,
+// List kinds: every nonzero connection of every sample, filed under its
+// first changed order position.  Heisenberg: the anti-aligned bonds (an
+// aligned pair has no off-diagonal element, Eq. 7); cluster: every term (its
+// off-diagonal element is +-J, never zero, Eq. 9).
+__global__ void conn_list(int ham_kind, const uint8_t *cfg, int64_t ns, int Lx, int Ly, int *cnt,
                           const int *list_off, int *list) {
-    const int nb = bond_count(Lx, Ly), N = Lx * Ly;
+    const int nb = conn_count(ham_kind, Lx, Ly), N = Lx * Ly;
     const int64_t total = ns * nb;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         int s = (int)(e / nb), b = (int)(e % nb);
-        int sa, sc;
-        bond_sites(b, Lx, Ly, sa, sc);
-        if (cfg[(int64_t)s * N + sa] == cfg[(int64_t)s * N + sc]) continue;
-        int pa = site_pos(sa, Lx), pc = site_pos(sc, Lx);
-        int p = pa < pc ? pa : pc;
+        if (ham_kind == VMC_HEISENBERG) {
+            int sa, sc;
+            bond_sites(b, Lx, Ly, sa, sc);
+            if (cfg[(int64_t)s * N + sa] == cfg[(int64_t)s * N + sc]) continue;
+        }
+        const int p = conn_first_pos(ham_kind, b, Lx, Ly);
         int slot = atomicAdd(&cnt[p], 1);
         list[list_off[p] + slot] = s * nb + b;
     }
@@ -254,15 +263,17 @@ __global__ void tile_scan(int N, int MT, const int *cnt, int *tile_start) {
     }
 }
 
-// E_loc assembly (Eqs. 6, 7): diagonal part from the bonds, off-diagonal
-// part sum_k coupling * psi(sigma')/psi(sigma), where
+// E_loc assembly (Eqs. 6-9): diagonal part (bonds; all pairs for the
+// long-range TFIM; none for the cluster state), off-diagonal part
+// sum_k coupling * psi(sigma')/psi(sigma), where
 //   log psi(sigma') - log psi(sigma) =
 //       [lpc[p][sigma'_p] - lpc[p][sigma_p]]              (head at p)
 //     + [chain sum after p] - [original sum after p]     (suffix)
 // halved for |psi|; the original suffix sum is pre[N-1] - pre[p] (FP64).
 // FP64 sums in a fixed order (see below).
-__global__ __launch_bounds__(256) void eloc_assemble(int ham_kind, int marshall, int cplx, double J, double hx, int Lx,
-                                                     int Ly, int64_t ns, const uint8_t *cfg, const float *lpc,
+__global__ __launch_bounds__(256) void eloc_assemble(int ham_kind, int marshall, int cplx, double J, double hx,
+                                                     double alpha, int Lx, int Ly, int64_t ns, const uint8_t *cfg,
+                                                     const float *lpc,
                                                      const float *phc, const double2 *pre, const double2 *dsuf, int NC,
                                                      double *eloc) {
     // 16 lanes per sample, each over every 16th connection (and bond of the
@@ -273,10 +284,19 @@ __global__ __launch_bounds__(256) void eloc_assemble(int ham_kind, int marshall,
     for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4; s < ns; s += step) {
         const uint8_t *c = cfg + s * N;
         double diag = 0.0, ore = 0.0, oim = 0.0;
-        for (int b = sub; b < nb; b += 16) {
-            int sa, sc;
-            bond_sites(b, Lx, Ly, sa, sc);
-            diag += (c[sa] == c[sc]) ? 1.0 : -1.0;
+        if (ham_kind == VMC_LRTFIM) {
+            // sum_{i<j} s_i s_j / |i-j|^alpha, by distance d (Eq. 8)
+            for (int dd = 1 + sub; dd < N; dd += 16) {
+                int agree = 0;
+                for (int i = 0; i + dd < N; i++) agree += (c[i] == c[i + dd]) ? 1 : -1;
+                diag += (double)agree * pow((double)dd, -alpha);
+            }
+        } else if (ham_kind != VMC_CLUSTER) {
+            for (int b = sub; b < nb; b += 16) {
+                int sa, sc;
+                bond_sites(b, Lx, Ly, sa, sc);
+                diag += (c[sa] == c[sc]) ? 1.0 : -1.0;
+            }
         }
         const float *lr = lpc + s * N * 2, *pr = phc + s * N * 2;
         const double2 *pp = pre + s * N;
@@ -299,8 +319,18 @@ __global__ __launch_bounds__(256) void eloc_assemble(int ham_kind, int marshall,
                 ore += coef * mag;  // a positive RNN has no phase
             }
         };
-        if (ham_kind == 0) {
+        if (ham_kind == VMC_TFIM || ham_kind == VMC_LRTFIM) {
             for (int p = sub; p < N; p += 16) ratio(p, p < N - 1 ? dsuf[s * NC + p] : make_double2(0.0, 0.0), -hx);
+        } else if (ham_kind == VMC_CLUSTER) {
+            // -J times the Z eigenvalues of the term (1D: position = site)
+            for (int t = sub; t < N; t += 16) {
+                int f1, f2, z1, z2;
+                cluster_term(t, N, f1, f2, z1, z2);
+                double coef = -J;
+                if (z1 >= 0 && c[z1]) coef = -coef;
+                if (z2 >= 0 && c[z2]) coef = -coef;
+                ratio(f2 >= 0 && f2 < f1 ? f2 : f1, dsuf[s * NC + t], coef);
+            }
         } else {
             const double jx = (marshall ? -0.5 : 0.5) * J;
             for (int b = sub; b < nb; b += 16) {
@@ -318,7 +348,8 @@ __global__ __launch_bounds__(256) void eloc_assemble(int ham_kind, int marshall,
             oim += __shfl_xor(oim, m, 16);
         }
         if (sub == 0) {
-            eloc[2 * s] = diag * (ham_kind == 0 ? -J : 0.25 * J) + ore;
+            const double dscale = ham_kind == VMC_HEISENBERG ? 0.25 * J : -J;
+            eloc[2 * s] = (ham_kind == VMC_CLUSTER ? 0.0 : diag * dscale) + ore;
             eloc[2 * s + 1] = oim;
         }
     }
@@ -352,12 +383,12 @@ hipError_t launch_sched(int ham_kind, int Lx, int Ly, int64_t ns, const uint8_t 
                         int *list_off, int *list, int *tile_start, int *tile_counter, int MT,
                         hipStream_t st) {
     hipLaunchKernelGGL(sched_prep, dim3(1), dim3(1024), 0, st, ham_kind, Lx, Ly, ns, cnt, list_off, tile_counter);
-    if (ham_kind == 1) {
-        int64_t total = ns * bond_count(Lx, Ly);
+    if (ham_kind != 0) {
+        int64_t total = ns * conn_count(ham_kind, Lx, Ly);
         int grid = (int)((total + 255) / 256);
         if (grid > 8192) grid = 8192;
         if (grid < 1) grid = 1;
-        hipLaunchKernelGGL(heis_list, dim3(grid), dim3(256), 0, st, cfg, ns, Lx, Ly, cnt, list_off, list);
+        hipLaunchKernelGGL(conn_list, dim3(grid), dim3(256), 0, st, ham_kind, cfg, ns, Lx, Ly, cnt, list_off, list);
     }
     hipLaunchKernelGGL(tile_scan, dim3(1), dim3(64), 0, st, Lx * Ly, MT, cnt, tile_start);
     return hipGetLastError();
@@ -368,8 +399,8 @@ hipError_t launch_assemble(const vmc_ham &H, int cplx, int Lx, int Ly, int64_t n
                            double *eloc, hipStream_t st) {
     int64_t g = (ns * 16 + 255) / 256;
     const int grid = (int)(g < 1 ? 1 : g > 65536 ? 65536 : g);
-    hipLaunchKernelGGL(eloc_assemble, dim3(grid), dim3(256), 0, st, H.kind, H.marshall, cplx, H.J, H.h, Lx, Ly, ns,
-                       cfg, lpc, phc, pre, dsuf, NC, eloc);
+    hipLaunchKernelGGL(eloc_assemble, dim3(grid), dim3(256), 0, st, H.kind, H.marshall, cplx, H.J, H.h, H.alpha, Lx,
+                       Ly, ns, cfg, lpc, phc, pre, dsuf, NC, eloc);
     return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@ struct FwdArgs {
     const uint8_t *cfg_in;   // [ns][N] lattice order (LOGPSI, CHAIN)
     const float *uniforms;   // [ns][N] order-indexed or NULL (SAMPLE)
     uint64_t seed, counter;  // Philox (SAMPLE without uniforms)
+    const uint64_t *counter_dev;  // device-resident Philox counter (replaces `counter` when set)
     // outputs
     uint8_t *cfg_out;        // SAMPLE
     float *logp, *phase;     // SAMPLE/LOGPSI, may be NULL
@@ -32,7 +33,8 @@ struct FwdArgs {
     // per-workgroup scratch: column buffer of the 2D chain [grid][Lx][MT][DH]
     void *colbuf;
     // CHAIN mode
-    int ham_kind;            // 0 TFIM, 1 Heisenberg
+    int ham_kind;            // connection kind: 0 one flip per position (TFIM, LR-TFIM),
+                             // 1 Heisenberg bond, 3 cluster term (see conn_sites)
     int nbond;
     const int *cnt, *tile_start, *list_off, *list;
     int *tile_counter;
@@ -126,6 +128,38 @@ __host__ __device__ inline void bond_sites(int b, int Lx, int Ly, int &a, int &c
         int i = b - (Ly - 1) * per;
         a = (Ly - 1) * Lx + i;
         c = a + 1;
+    }
+}
+
+// Terms of the 1D cluster Hamiltonian (Eq. 9), 0-indexed sites, t < N:
+//   t <= N-4: X_t Z_{t+1} X_{t+2}      (flips t, t+2; sign from site t+1)
+//   t  = N-3: Z_0 X_1                   (flips 1;      sign from site 0)
+//   t  = N-2: X_{N-2} X_{N-1}           (flips N-2, N-1)
+//   t  = N-1: X_{N-3} Z_{N-2} Z_{N-1}   (flips N-3;    signs from N-2, N-1)
+// f2, z1, z2 = -1 where absent.
+__host__ __device__ inline void cluster_term(int t, int N, int &f1, int &f2, int &z1, int &z2) {
+    if (t <= N - 4) {
+        f1 = t; f2 = t + 2; z1 = t + 1; z2 = -1;
+    } else if (t == N - 3) {
+        f1 = 1; f2 = -1; z1 = 0; z2 = -1;
+    } else if (t == N - 2) {
+        f1 = N - 2; f2 = N - 1; z1 = -1; z2 = -1;
+    } else {
+        f1 = N - 3; f2 = -1; z1 = N - 2; z2 = N - 1;
+    }
+}
+
+// Connections per sample of a list-scheduled connection kind (1 Heisenberg,
+// 3 cluster) and the sites connection c flips (b = -1 for a single flip).
+__host__ __device__ inline int conn_count(int kind, int Lx, int Ly) {
+    return kind == VMC_CLUSTER ? Lx * Ly : bond_count(Lx, Ly);
+}
+__host__ __device__ inline void conn_sites(int kind, int c, int Lx, int Ly, int &a, int &b) {
+    if (kind == VMC_CLUSTER) {
+        int z1, z2;
+        cluster_term(c, Lx * Ly, a, b, z1, z2);
+    } else {
+        bond_sites(c, Lx, Ly, a, b);
     }
 }
 

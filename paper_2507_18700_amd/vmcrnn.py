@@ -15,11 +15,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("VMCRNN_LIB") or os.path.join(_HERE, "libvmcrnn.so")
 
 VMC_FP32, VMC_BF16 = 0, 1
-VMC_TFIM, VMC_HEISENBERG = 0, 1
+VMC_TFIM, VMC_HEISENBERG, VMC_LRTFIM, VMC_CLUSTER = 0, 1, 2, 3
+VMC_EINVAL, VMC_EUNSUPPORTED, VMC_ENOSPACE, VMC_EDEVICE, VMC_ENONFINITE = -1, -2, -3, -4, -5
 
 EXPORTS = ("vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "rnn_logpsi_grad", "local_energy",
-           "vmc_grad", "vmc_step", "grow_hidden", "vmc_row_tile_options", "vmc_set_tuning", "vmc_get_tuning",
-           "vmc_autotune_step", "vmc_chain_timing", "vmc_chain_time", "vmc_status_str")
+           "vmc_grad", "vmc_step", "vmc_adam", "vmc_check_finite", "grow_hidden", "vmc_row_tile_options",
+           "vmc_set_tuning", "vmc_get_tuning", "vmc_autotune_step", "vmc_chain_timing", "vmc_chain_time",
+           "vmc_status_str")
 
 
 class VmcError(RuntimeError):
@@ -40,7 +42,13 @@ class Model(ctypes.Structure):
 
 class Ham(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("marshall", ctypes.c_int32), ("J", ctypes.c_double),
-                ("h", ctypes.c_double)]
+                ("h", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
+class AdamCfg(ctypes.Structure):
+    _fields_ = [("lr0", ctypes.c_double), ("lr1", ctypes.c_double), ("t_switch", ctypes.c_int64),
+                ("t_decay", ctypes.c_int64), ("tau", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -51,8 +59,14 @@ def model(dims=1, Lx=4, Ly=1, d_h=16, is_complex=False, glu=False, precision=VMC
     return Model(dims, Lx, Ly if dims == 2 else 1, d_h, int(is_complex), int(glu), int(precision))
 
 
-def ham(kind=VMC_TFIM, J=1.0, h=1.0, marshall=False):
-    return Ham(kind, int(marshall), float(J), float(h))
+def ham(kind=VMC_TFIM, J=1.0, h=1.0, marshall=False, alpha=0.0):
+    return Ham(kind, int(marshall), float(J), float(h), float(alpha))
+
+
+def adam_cfg(lr0=1e-3, lr1=None, t_switch=0, t_decay=0, tau=0.0, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Adam settings; lr(k) = (k < t_switch ? lr0 : lr1) / (1 + max(0, k - t_decay) / tau)."""
+    return AdamCfg(float(lr0), float(lr0 if lr1 is None else lr1), int(t_switch), int(t_decay), float(tau),
+                   float(beta1), float(beta2), float(eps))
 
 
 _lib = None
@@ -83,7 +97,11 @@ def lib():
         L.vmc_grad.restype = ctypes.c_int
         L.vmc_grad.argtypes = [P(Model), vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
         L.vmc_step.restype = ctypes.c_int
-        L.vmc_step.argtypes = [P(Model), vp, P(Ham), i64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.vmc_step.argtypes = [P(Model), vp, P(Ham), i64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.vmc_adam.restype = ctypes.c_int
+        L.vmc_adam.argtypes = [i64, vp, vp, vp, vp, vp, P(AdamCfg), vp]
+        L.vmc_check_finite.restype = ctypes.c_int
+        L.vmc_check_finite.argtypes = [vp, i64, P(i64), vp, sz, vp]
         L.grow_hidden.restype = ctypes.c_int
         L.grow_hidden.argtypes = [P(Model), vp, ctypes.c_int32, u64, d, vp, vp, vp, vp, vp, vp]
         L.vmc_row_tile_options.restype = ctypes.c_int
@@ -118,10 +136,39 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _dev(t, dtype, name):
+def _dev(t, dtype, name, shape=None):
+    """Checks a device argument before any launch: the C ABI cannot check
+    lengths, so a short or mis-typed buffer would be read or written past
+    its end on the GPU."""
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
         raise TypeError("%s must be a contiguous %s tensor on the GPU" % (name, dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
     return t
+
+
+def _params(m, params):
+    return _dev(params, torch.float32, "params", (param_count(m),))
+
+
+def _configs(m, configs):
+    _dev(configs, torch.uint8, "configs")
+    if configs.dim() != 2 or configs.shape[1] != m.N or configs.shape[0] < 1:
+        raise ValueError("configs must have shape [n, N=%d] with n >= 1, got %s" % (m.N, tuple(configs.shape)))
+    return configs.shape[0]
+
+
+def _step_out(m, ns, out):
+    """Checks a caller-supplied (configs, logp, phase, eloc, grad, stats) tuple."""
+    cfg, lp, ph, e, g, st = out
+    _dev(cfg, torch.uint8, "configs", (ns, m.N))
+    _dev(lp, torch.float32, "logp", (ns,))
+    if ph is not None:
+        _dev(ph, torch.float32, "phase", (ns,))
+    _dev(e, torch.float64, "eloc", (ns, 2))
+    _dev(g, torch.float64, "grad", (param_count(m),))
+    _dev(st, torch.float64, "stats", (4,))
+    return out
 
 
 def param_count(m):
@@ -166,17 +213,19 @@ def _ws(ws, m, H, ns):
 
 def rnn_sample(m, params, ns, seed=0, counter=0, uniforms=None, ws=None, out=None):
     """Autoregressive sampling; returns (configs uint8 [ns,N], logp [ns], phase [ns])."""
-    _dev(params, torch.float32, "params")
+    _params(m, params)
     dev = params.device
     if uniforms is not None:
-        _dev(uniforms, torch.float32, "uniforms")
-        if uniforms.shape != (ns, m.N):
-            raise ValueError("uniforms must have shape [ns, N]")
+        _dev(uniforms, torch.float32, "uniforms", (ns, m.N))
     if out is None:
         out = (torch.empty((ns, m.N), dtype=torch.uint8, device=dev),
                torch.empty(ns, dtype=torch.float32, device=dev),
                torch.empty(ns, dtype=torch.float32, device=dev))
     cfg, lp, ph = out
+    _dev(cfg, torch.uint8, "configs", (ns, m.N))
+    _dev(lp, torch.float32, "logp", (ns,))
+    if ph is not None:
+        _dev(ph, torch.float32, "phase", (ns,))
     buf, nb = _ws(ws, m, None, ns)
     _check(lib().rnn_sample(ctypes.byref(m), _ptr(params), ns, seed, counter, _ptr(uniforms), _ptr(cfg),
                             _ptr(lp), _ptr(ph), _ptr(buf), nb, _stream()))
@@ -185,9 +234,8 @@ def rnn_sample(m, params, ns, seed=0, counter=0, uniforms=None, ws=None, out=Non
 
 def rnn_logpsi(m, params, configs, ws=None):
     """Teacher-forced (logp [nc], phase [nc]) of given configurations."""
-    _dev(params, torch.float32, "params")
-    _dev(configs, torch.uint8, "configs")
-    nc = configs.shape[0]
+    _params(m, params)
+    nc = _configs(m, configs)
     lp = torch.empty(nc, dtype=torch.float32, device=params.device)
     ph = torch.empty(nc, dtype=torch.float32, device=params.device)
     buf, nb = _ws(ws, m, None, nc)
@@ -199,13 +247,13 @@ def rnn_logpsi(m, params, configs, ws=None):
 def rnn_logpsi_grad(m, params, configs, dlogp, dphase=None, ws=None, out=None):
     """Vector-Jacobian product of rnn_logpsi: sum_s dlogp_s d logP_s + dphase_s d phi_s,
     float64 [P]."""
-    _dev(params, torch.float32, "params")
-    _dev(configs, torch.uint8, "configs")
-    _dev(dlogp, torch.float32, "dlogp")
+    _params(m, params)
+    nc = _configs(m, configs)
+    _dev(dlogp, torch.float32, "dlogp", (nc,))
     if dphase is not None:
-        _dev(dphase, torch.float32, "dphase")
-    nc = configs.shape[0]
+        _dev(dphase, torch.float32, "dphase", (nc,))
     g = out if out is not None else torch.empty(param_count(m), dtype=torch.float64, device=params.device)
+    _dev(g, torch.float64, "grad", (param_count(m),))
     buf, nb = _ws(ws, m, None, nc)
     _check(lib().rnn_logpsi_grad(ctypes.byref(m), _ptr(params), nc, _ptr(configs), _ptr(dlogp), _ptr(dphase),
                                  _ptr(g), _ptr(buf), nb, _stream()))
@@ -241,10 +289,10 @@ def logpsi(m, params, configs):
 
 def local_energy(m, params, H, configs, ws=None, out=None):
     """Local energies [ns, 2] float64 (real, imaginary)."""
-    _dev(params, torch.float32, "params")
-    _dev(configs, torch.uint8, "configs")
-    ns = configs.shape[0]
+    _params(m, params)
+    ns = _configs(m, configs)
     e = out if out is not None else torch.empty((ns, 2), dtype=torch.float64, device=params.device)
+    _dev(e, torch.float64, "eloc", (ns, 2))
     buf, nb = _ws(ws, m, H, ns)
     _check(lib().local_energy(ctypes.byref(m), _ptr(params), ctypes.byref(H), ns, _ptr(configs), _ptr(e),
                               _ptr(buf), nb, _stream()))
@@ -253,31 +301,37 @@ def local_energy(m, params, H, configs, ws=None, out=None):
 
 def vmc_grad(m, params, configs, eloc, weights=None, ws=None, out=None):
     """Covariance energy gradient; returns (grad float64 [P], stats float64 [4])."""
-    _dev(params, torch.float32, "params")
-    _dev(configs, torch.uint8, "configs")
-    _dev(eloc, torch.float64, "eloc")
+    _params(m, params)
+    ns = _configs(m, configs)
+    _dev(eloc, torch.float64, "eloc", (ns, 2))
     if weights is not None:
-        _dev(weights, torch.float64, "weights")
-    ns = configs.shape[0]
+        _dev(weights, torch.float64, "weights", (ns,))
     if out is None:
         out = (torch.empty(param_count(m), dtype=torch.float64, device=params.device),
                torch.empty(4, dtype=torch.float64, device=params.device))
     g, st = out
+    _dev(g, torch.float64, "grad", (param_count(m),))
+    _dev(st, torch.float64, "stats", (4,))
     buf, nb = _ws(ws, m, None, ns)
     _check(lib().vmc_grad(ctypes.byref(m), _ptr(params), ns, _ptr(configs), _ptr(eloc), _ptr(weights), _ptr(g),
                           _ptr(st), _ptr(buf), nb, _stream()))
     return g, st
 
 
-def vmc_step(m, params, H, ns, seed=0, counter=0, uniforms=None, ws=None, out=None):
+def vmc_step(m, params, H, ns, seed=0, counter=0, uniforms=None, ws=None, out=None, counter_dev=None):
     """One VMC step (sample, local energy, gradient with w = 1/ns) sharing one
-    forward pass; returns (configs, logp, phase, eloc, grad, stats)."""
-    _dev(params, torch.float32, "params")
+    forward pass; returns (configs, logp, phase, eloc, grad, stats).
+    counter_dev: optional one-element uint64 (int64) device tensor that
+    replaces `counter` and is advanced by one at the end of the step, so that
+    replays of a captured graph draw fresh samples."""
+    _params(m, params)
     dev = params.device
     if uniforms is not None:
-        _dev(uniforms, torch.float32, "uniforms")
-        if uniforms.shape != (ns, m.N):
-            raise ValueError("uniforms must have shape [ns, N]")
+        _dev(uniforms, torch.float32, "uniforms", (ns, m.N))
+    if counter_dev is not None and not (isinstance(counter_dev, torch.Tensor) and counter_dev.is_cuda and
+                                        counter_dev.dtype in (torch.int64, torch.uint64) and
+                                        counter_dev.numel() == 1):
+        raise TypeError("counter_dev must be a one-element int64/uint64 tensor on the GPU")
     if out is None:
         out = (torch.empty((ns, m.N), dtype=torch.uint8, device=dev),
                torch.empty(ns, dtype=torch.float32, device=dev),
@@ -285,23 +339,51 @@ def vmc_step(m, params, H, ns, seed=0, counter=0, uniforms=None, ws=None, out=No
                torch.empty((ns, 2), dtype=torch.float64, device=dev),
                torch.empty(param_count(m), dtype=torch.float64, device=dev),
                torch.empty(4, dtype=torch.float64, device=dev))
-    cfg, lp, ph, e, g, st = out
+    cfg, lp, ph, e, g, st = _step_out(m, ns, out)
     buf, nb = _ws(ws, m, H, ns)
-    _check(lib().vmc_step(ctypes.byref(m), _ptr(params), ctypes.byref(H), ns, seed, counter, _ptr(uniforms),
-                          _ptr(cfg), _ptr(lp), _ptr(ph), _ptr(e), _ptr(g), _ptr(st), _ptr(buf), nb, _stream()))
+    _check(lib().vmc_step(ctypes.byref(m), _ptr(params), ctypes.byref(H), ns, seed, counter, _ptr(counter_dev),
+                          _ptr(uniforms), _ptr(cfg), _ptr(lp), _ptr(ph), _ptr(e), _ptr(g), _ptr(st), _ptr(buf), nb,
+                          _stream()))
     return cfg, lp, ph, e, g, st
+
+
+def adam(params, grad, m_mom, v_mom, t_dev, cfg):
+    """Adam update of the float32 parameters (in place) from a float64
+    gradient; m_mom, v_mom float32 moments; t_dev a one-element int64 device
+    tensor of updates done (advanced by the call)."""
+    n = params.numel()
+    _dev(params, torch.float32, "params")
+    _dev(grad, torch.float64, "grad", (n,))
+    _dev(m_mom, torch.float32, "m", (n,))
+    _dev(v_mom, torch.float32, "v", (n,))
+    _dev(t_dev, torch.int64, "t_dev", (1,))
+    _check(lib().vmc_adam(n, _ptr(params), _ptr(grad), _ptr(m_mom), _ptr(v_mom), _ptr(t_dev), ctypes.byref(cfg),
+                          _stream()))
+
+
+def check_finite(x, ws=None):
+    """Number of non-finite entries of a float32 device tensor (synchronous);
+    raises VmcError(VMC_ENONFINITE) if there are any."""
+    _dev(x, torch.float32, "x")
+    if ws is None:
+        dev = torch.cuda.current_device()
+        ws = _default_ws.setdefault(dev, Workspace("cuda:%d" % dev))
+    buf = ws.get(256)
+    cnt = ctypes.c_int64(0)
+    _check(lib().vmc_check_finite(_ptr(x), x.numel(), ctypes.byref(cnt), _ptr(buf), buf.numel(), _stream()))
+    return cnt.value
 
 
 def grow_hidden(m, params, new_dh, seed, noise_std, m_mom=None, v_mom=None):
     """Grown parameters (and moments if given) at hidden width new_dh."""
-    _dev(params, torch.float32, "params")
+    _params(m, params)
     to = Model(m.dims, m.Lx, m.Ly, new_dh, m.is_complex, m.glu, m.precision)
     n1 = param_count(to)
     p1 = torch.empty(n1, dtype=torch.float32, device=params.device)
     mm = vv = None
     if m_mom is not None or v_mom is not None:
-        _dev(m_mom, torch.float32, "m")
-        _dev(v_mom, torch.float32, "v")
+        _dev(m_mom, torch.float32, "m", (params.numel(),))
+        _dev(v_mom, torch.float32, "v", (params.numel(),))
         mm = torch.empty_like(p1)
         vv = torch.empty_like(p1)
     _check(lib().grow_hidden(ctypes.byref(m), _ptr(params), new_dh, seed, float(noise_std), _ptr(p1),
@@ -338,10 +420,10 @@ def get_tuning(m):
 def autotune_step(m, params, H, ns, seed=0, counter=0, uniforms=None, ws=None, out=None, reps=3):
     """Autotuner: times vmc_step under each candidate launch choice, keeps the
     fastest in the library's table and returns (outputs of vmc_step, choice)."""
-    _dev(params, torch.float32, "params")
+    _params(m, params)
     dev = params.device
     if uniforms is not None:
-        _dev(uniforms, torch.float32, "uniforms")
+        _dev(uniforms, torch.float32, "uniforms", (ns, m.N))
     if out is None:
         out = (torch.empty((ns, m.N), dtype=torch.uint8, device=dev),
                torch.empty(ns, dtype=torch.float32, device=dev),
@@ -349,7 +431,7 @@ def autotune_step(m, params, H, ns, seed=0, counter=0, uniforms=None, ws=None, o
                torch.empty((ns, 2), dtype=torch.float64, device=dev),
                torch.empty(param_count(m), dtype=torch.float64, device=dev),
                torch.empty(4, dtype=torch.float64, device=dev))
-    cfg, lp, ph, e, g, st = out
+    cfg, lp, ph, e, g, st = _step_out(m, ns, out)
     buf, nb = _ws(ws, m, H, ns)
     t = Tuning()
     _check(lib().vmc_autotune_step(ctypes.byref(m), _ptr(params), ctypes.byref(H), ns, seed, counter,

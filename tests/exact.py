@@ -89,3 +89,28 @@ def ground_energy(H):
     if H.shape[0] <= 1024:
         return np.linalg.eigvalsh(H.toarray()).min()
     return sla.eigsh(H, k=1, which="SA")[0][0]
+
+
+def lrtfim(N, J, h, alpha):
+    """Long-range TFIM chain, Eq. (8): -J sum_{i<j} Z_i Z_j / |i-j|^alpha - h sum X."""
+    H = sp.csr_matrix((2 ** N, 2 ** N), dtype=complex)
+    for i in range(N):
+        for j in range(i + 1, N):
+            H = H - J / float(j - i) ** alpha * op_at({i: Z, j: Z}, N)
+    for k in range(N):
+        H = H - h * op_at({k: X}, N)
+    return H
+
+
+def cluster(n, J=1.0):
+    """1D cluster Hamiltonian, Eq. (9), sites 1..n in the paper's numbering
+    (0..n-1 here): -J [sum_{k=2}^{n-2} X_{k-1} Z_k X_{k+1} + Z_1 X_2
+    + X_{n-1} X_n + X_{n-2} Z_{n-1} Z_n]."""
+    H = sp.csr_matrix((2 ** n, 2 ** n), dtype=complex)
+    s = lambda k: k - 1  # paper site k -> index
+    for k in range(2, n - 1):
+        H = H - J * op_at({s(k - 1): X, s(k): Z, s(k + 1): X}, n)
+    H = H - J * op_at({s(1): Z, s(2): X}, n)
+    H = H - J * op_at({s(n - 1): X, s(n): X}, n)
+    H = H - J * op_at({s(n - 2): X, s(n - 1): Z, s(n): Z}, n)
+    return H

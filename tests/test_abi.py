@@ -32,9 +32,9 @@ def lib():
 def test_exports_every_declared_symbol(lib):
     names = declared()
     assert set(names) == {"vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "rnn_logpsi_grad",
-                          "local_energy", "vmc_grad", "vmc_step", "grow_hidden", "vmc_row_tile_options",
-                          "vmc_set_tuning", "vmc_get_tuning", "vmc_autotune_step", "vmc_chain_timing",
-                          "vmc_chain_time", "vmc_status_str"}
+                          "local_energy", "vmc_grad", "vmc_step", "vmc_adam", "vmc_check_finite", "grow_hidden",
+                          "vmc_row_tile_options", "vmc_set_tuning", "vmc_get_tuning", "vmc_autotune_step",
+                          "vmc_chain_timing", "vmc_chain_time", "vmc_status_str"}
     L = ctypes.CDLL(LIB)
     for n in names:
         assert hasattr(L, n), n
@@ -105,6 +105,54 @@ def test_argument_errors_before_launch(lib):
     assert L.vmc_autotune_step(ctypes.byref(m), fake, ctypes.byref(H), 100, 0, 0, None, None, fake, None, fake,
                                fake, fake, ws, need, None, 3, ctypes.byref(t)) == -1
     assert L.vmc_status_str(-3) == b"workspace too small"
+
+
+def test_nonfinite_and_hamiltonian_errors(lib):
+    """Non-finite couplings, noise and Adam settings give VMC_ENONFINITE, the
+    1D-only Hamiltonians on a 2D lattice VMC_EUNSUPPORTED, all on the host
+    before any launch (the fake device pointers are never dereferenced)."""
+    L = lib.lib()
+    inf, nan = float("inf"), float("nan")
+    m1 = lib.model(dims=1, Lx=12, d_h=16)
+    m2 = lib.model(dims=2, Lx=4, Ly=4, d_h=16, glu=True)
+    out = ctypes.c_size_t(0)
+    fake = ctypes.c_void_p(0x100000)
+    ws = ctypes.c_void_p(0x200000)
+    for H in (lib.ham(lib.VMC_TFIM, nan, 1.0), lib.ham(lib.VMC_TFIM, 1.0, inf),
+              lib.ham(lib.VMC_LRTFIM, 1.0, 1.0, alpha=nan), lib.ham(lib.VMC_CLUSTER, -inf, 0.0),
+              lib.ham(lib.VMC_HEISENBERG, nan, 0.0, True)):
+        assert L.vmc_workspace_size(ctypes.byref(m1), ctypes.byref(H), 10, ctypes.byref(out)) == lib.VMC_ENONFINITE
+        assert L.local_energy(ctypes.byref(m1), fake, ctypes.byref(H), 10, fake, fake, ws, 1 << 30, None) == \
+            lib.VMC_ENONFINITE
+        assert L.vmc_step(ctypes.byref(m1), fake, ctypes.byref(H), 10, 0, 0, None, None, fake, fake, None, fake,
+                          fake, fake, ws, 1 << 30, None) == lib.VMC_ENONFINITE
+    assert lib.VmcError(lib.VMC_ENONFINITE, "x").status == -5
+    assert L.vmc_status_str(-5) == b"non-finite value"
+    # 1D-only kinds on a lattice; negative exponent; a cluster chain needs n >= 3
+    for H in (lib.ham(lib.VMC_LRTFIM, 1.0, 1.0, alpha=1.0), lib.ham(lib.VMC_CLUSTER, 1.0)):
+        assert L.vmc_workspace_size(ctypes.byref(m2), ctypes.byref(H), 10, ctypes.byref(out)) == \
+            lib.VMC_EUNSUPPORTED
+    H = lib.ham(lib.VMC_LRTFIM, 1.0, 1.0, alpha=-0.5)
+    assert L.vmc_workspace_size(ctypes.byref(m1), ctypes.byref(H), 10, ctypes.byref(out)) == lib.VMC_EINVAL
+    H = lib.ham(lib.VMC_CLUSTER, 1.0)
+    m_2 = lib.model(dims=1, Lx=2, d_h=16)
+    assert L.vmc_workspace_size(ctypes.byref(m_2), ctypes.byref(H), 10, ctypes.byref(out)) == lib.VMC_EINVAL
+    for n in (3, 12):
+        m = lib.model(dims=1, Lx=n, d_h=16)
+        assert L.vmc_workspace_size(ctypes.byref(m), ctypes.byref(H), 10, ctypes.byref(out)) == 0
+    # grow_hidden noise
+    assert L.grow_hidden(ctypes.byref(m1), fake, 32, 0, inf, fake, None, None, None, None, None) == lib.VMC_ENONFINITE
+    assert L.grow_hidden(ctypes.byref(m1), fake, 32, 0, nan, fake, None, None, None, None, None) == lib.VMC_ENONFINITE
+    # Adam settings
+    t = ctypes.c_void_p(0x300000)
+    for cfg, want in ((lib.adam_cfg(lr0=nan), lib.VMC_ENONFINITE), (lib.adam_cfg(eps=inf), lib.VMC_ENONFINITE),
+                      (lib.adam_cfg(beta1=1.0), lib.VMC_EINVAL), (lib.adam_cfg(eps=0.0), lib.VMC_EINVAL),
+                      (lib.adam_cfg(lr0=-1e-3), lib.VMC_EINVAL), (lib.adam_cfg(tau=-1.0), lib.VMC_EINVAL)):
+        assert L.vmc_adam(100, fake, fake, fake, fake, t, ctypes.byref(cfg), None) == want
+    assert L.vmc_adam(0, fake, fake, fake, fake, t, ctypes.byref(lib.adam_cfg()), None) == lib.VMC_EINVAL
+    # the synchronous finiteness check validates its workspace first
+    assert L.vmc_check_finite(fake, 10, None, ws, 255, None) == lib.VMC_EINVAL
+    assert L.vmc_check_finite(fake, 10, None, ctypes.c_void_p(0x200010), 1024, None) == lib.VMC_EINVAL
 
 
 def test_workspace_grows_with_samples(lib):
