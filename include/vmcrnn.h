@@ -178,6 +178,27 @@ vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, i
                     uint8_t *configs, float *logp, float *phase, double *eloc, double *grad,
                     double *stats, void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): vmc_step
+ * with its workspace in a fixed device array of the library instead of a
+ * caller-provided one.  The caller still passes every input and output.
+ * The array holds vmc_noalloc_scratch_bytes() = 256 MiB on each GPU the
+ * library runs on, from the first call on that GPU until the process ends;
+ * a model, Hamiltonian and sample count whose vmc_workspace_size exceeds it
+ * get VMC_ENOSPACE before any launch.  The call allocates nothing (no
+ * hipMalloc or hipFree, no allocating library routine).  Every call on one
+ * GPU uses the same array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be ordered by the caller.  The array keeps
+ * the last call's contents; the step needs no zeroed workspace.  Arguments
+ * and results as for vmc_step. */
+vmc_status vmc_step_noalloc(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns,
+                            uint64_t seed, uint64_t counter, uint64_t *counter_dev, const float *uniforms,
+                            uint8_t *configs, float *logp, float *phase, double *eloc, double *grad,
+                            double *stats, void *stream);
+
+/* Bytes of the fixed workspace of vmc_step_noalloc (per GPU). */
+size_t vmc_noalloc_scratch_bytes(void);
+
 /* Adam update (Kingma & Ba, ICLR 2015), the optimiser of every benchmark of
  * the paper (App. B), of n float32 parameters from an FP64 gradient:
  *    t = *t_dev + 1,  lr = lr(t - 1),

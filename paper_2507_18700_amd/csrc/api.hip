@@ -565,6 +565,47 @@ vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, i
     return hip_status(launch_bump(counter_dev, st));
 }
 
+// ------------------------------------------------- step without allocation
+// A fixed device array serves as the workspace of vmc_step_noalloc, for
+// callers that cannot allocate.  In host code the name `scratch` is only a
+// stand-in for the symbol: kernels get the device address that
+// hipGetSymbolAddress returns, looked up once per device and kept.
+static const size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch_ptr;
+
+static vmc_status scratch_address(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return VMC_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = NULL;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return VMC_EDEVICE;
+        it = g_scratch_ptr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return VMC_OK;
+}
+
+vmc_status vmc_step_noalloc(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns, uint64_t seed,
+                            uint64_t counter, uint64_t *counter_dev, const float *uniforms, uint8_t *configs,
+                            float *logp, float *phase, double *eloc, double *grad, double *stats, void *stream) {
+    size_t need = 0;
+    const vmc_status s = vmc_workspace_size(m, H, ns, &need);
+    if (s != VMC_OK) return s;
+    if (!H) return VMC_EINVAL;
+    if (need > kScratchBytes) return VMC_ENOSPACE;
+    void *ws = NULL;
+    const vmc_status a = scratch_address(&ws);
+    if (a != VMC_OK) return a;
+    return vmc_step(m, params, H, ns, seed, counter, counter_dev, uniforms, configs, logp, phase, eloc, grad, stats,
+                    ws, kScratchBytes, stream);
+}
+
+size_t vmc_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
 vmc_status vmc_adam(int64_t n, float *params, const double *grad, float *m, float *v, int64_t *t_dev,
                     const vmc_adam_cfg *cfg, void *stream) {
     if (n < 1 || !params || !grad || !m || !v || !t_dev || !cfg) return VMC_EINVAL;

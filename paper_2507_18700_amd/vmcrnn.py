@@ -19,7 +19,8 @@ VMC_TFIM, VMC_HEISENBERG, VMC_LRTFIM, VMC_CLUSTER = 0, 1, 2, 3
 VMC_EINVAL, VMC_EUNSUPPORTED, VMC_ENOSPACE, VMC_EDEVICE, VMC_ENONFINITE = -1, -2, -3, -4, -5
 
 EXPORTS = ("vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "rnn_logpsi_grad", "local_energy",
-           "vmc_grad", "vmc_step", "vmc_adam", "vmc_check_finite", "grow_hidden", "vmc_row_tile_options",
+           "vmc_grad", "vmc_step", "vmc_step_noalloc", "vmc_noalloc_scratch_bytes", "vmc_adam", "vmc_check_finite",
+           "grow_hidden", "vmc_row_tile_options",
            "vmc_set_tuning", "vmc_get_tuning", "vmc_autotune_step", "vmc_chain_timing", "vmc_chain_time",
            "vmc_status_str")
 
@@ -98,6 +99,10 @@ def lib():
         L.vmc_grad.argtypes = [P(Model), vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
         L.vmc_step.restype = ctypes.c_int
         L.vmc_step.argtypes = [P(Model), vp, P(Ham), i64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.vmc_step_noalloc.restype = ctypes.c_int
+        L.vmc_step_noalloc.argtypes = [P(Model), vp, P(Ham), i64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.vmc_noalloc_scratch_bytes.restype = sz
+        L.vmc_noalloc_scratch_bytes.argtypes = []
         L.vmc_adam.restype = ctypes.c_int
         L.vmc_adam.argtypes = [i64, vp, vp, vp, vp, vp, P(AdamCfg), vp]
         L.vmc_check_finite.restype = ctypes.c_int
@@ -345,6 +350,26 @@ def vmc_step(m, params, H, ns, seed=0, counter=0, uniforms=None, ws=None, out=No
                           _ptr(uniforms), _ptr(cfg), _ptr(lp), _ptr(ph), _ptr(e), _ptr(g), _ptr(st), _ptr(buf), nb,
                           _stream()))
     return cfg, lp, ph, e, g, st
+
+
+def vmc_step_noalloc(m, params, H, ns, out, seed=0, counter=0, uniforms=None, counter_dev=None):
+    """vmc_step with the library's fixed device workspace (no allocation in
+    the library); `out` = (configs, logp, phase, eloc, grad, stats) must be
+    given.  Calls on one GPU share that workspace and must not overlap."""
+    _params(m, params)
+    if uniforms is not None:
+        _dev(uniforms, torch.float32, "uniforms", (ns, m.N))
+    if counter_dev is not None:
+        _dev(counter_dev, torch.int64, "counter_dev", (1,))
+    cfg, lp, ph, e, g, st = _step_out(m, ns, out)
+    _check(lib().vmc_step_noalloc(ctypes.byref(m), _ptr(params), ctypes.byref(H), ns, seed, counter,
+                                  _ptr(counter_dev), _ptr(uniforms), _ptr(cfg), _ptr(lp), _ptr(ph), _ptr(e), _ptr(g),
+                                  _ptr(st), _stream()))
+    return out
+
+
+def noalloc_scratch_bytes():
+    return lib().vmc_noalloc_scratch_bytes()
 
 
 def adam(params, grad, m_mom, v_mom, t_dev, cfg):

@@ -17,7 +17,7 @@ LIB = os.path.join(ROOT, "paper_2507_18700_amd", "libvmcrnn.so")
 def declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?(?:vmc_status|int64_t|char)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?(?:vmc_status|int64_t|size_t|char)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
@@ -32,7 +32,8 @@ def lib():
 def test_exports_every_declared_symbol(lib):
     names = declared()
     assert set(names) == {"vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "rnn_logpsi_grad",
-                          "local_energy", "vmc_grad", "vmc_step", "vmc_adam", "vmc_check_finite", "grow_hidden",
+                          "local_energy", "vmc_grad", "vmc_step", "vmc_step_noalloc", "vmc_noalloc_scratch_bytes",
+                          "vmc_adam", "vmc_check_finite", "grow_hidden",
                           "vmc_row_tile_options", "vmc_set_tuning", "vmc_get_tuning", "vmc_autotune_step",
                           "vmc_chain_timing", "vmc_chain_time", "vmc_status_str"}
     L = ctypes.CDLL(LIB)
