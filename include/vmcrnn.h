@@ -178,6 +178,36 @@ vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, i
                     uint8_t *configs, float *logp, float *phase, double *eloc, double *grad,
                     double *stats, void *ws, size_t ws_bytes, void *stream);
 
+/* Several independent 1D problems in one call (uneven chains or couplings;
+ * the batched VMC step of Sec. III, one per problem): problem k is a chain of
+ * chain_len[k] sites with the cell shape of m (d_h, precision, is_complex,
+ * glu; m->dims must be 1, m->Lx is ignored), Hamiltonian H[k] (all of the
+ * same kind, couplings free) and parameters params + k*P (P =
+ * vmc_param_count of that shape), and its outputs equal, bit for bit, those
+ * of vmc_step on that problem alone with Philox key seed + k and the same
+ * counter.  The launches are shared: one sampling launch over the tiles of
+ * every problem, one persistent suffix-chain launch over every connected
+ * configuration of every sample of every problem (one queue, longest chains
+ * first), one reverse sweep and one weight-gradient contraction per
+ * segment.  At most 64 problems, all with ns samples.
+ *  params:  [nprob][P] float.
+ *  configs: [nprob][ns * Nmax] uint8; problem k's [ns][chain_len[k]]
+ *           configurations start at k * ns * Nmax (Nmax = the longest chain).
+ *  logp, phase: [nprob][ns] float (phase may be NULL).
+ *  eloc: [nprob][ns][2] double; grad: [nprob][P] double; stats: [nprob][4].
+ *  counter_dev: as in vmc_step (one counter for the batch).
+ *  ws: at least vmc_batched_workspace_size() bytes. */
+vmc_status vmc_step_batched(int32_t nprob, const vmc_model *m, const int32_t *chain_len, const vmc_ham *H,
+                            const float *params, int64_t ns, uint64_t seed, uint64_t counter,
+                            uint64_t *counter_dev, uint8_t *configs, float *logp, float *phase,
+                            double *eloc, double *grad, double *stats, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* Workspace bytes of vmc_step_batched with these arguments (chain_len and H
+ * are host arrays of nprob entries). */
+vmc_status vmc_batched_workspace_size(int32_t nprob, const vmc_model *m, const int32_t *chain_len,
+                                      const vmc_ham *H, int64_t ns, size_t *bytes);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): vmc_step
  * with its workspace in a fixed device array of the library instead of a

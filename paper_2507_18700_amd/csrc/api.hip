@@ -15,7 +15,7 @@ namespace vmc {
 hipError_t launch_stage(const Dims &d, const float *prm, void *Bc, void *BcT, void *Bg, void *BgT,
                         float *E, float *Hd, float *hc, int4 *postab, hipStream_t st);
 hipError_t launch_forward(const FwdArgs &a, int mode, int store_h, int store_lpc, int store_act,
-                          int grid, hipStream_t st);
+                          int grid, hipStream_t st, const BatchInfo *bi = nullptr);
 hipError_t launch_sched(int ham_kind, int Lx, int Ly, int64_t ns, const uint8_t *cfg, int *cnt,
                         int *list_off, int *list, int *tile_start, int *tile_counter, int MT,
                         hipStream_t st);
@@ -31,7 +31,7 @@ int chain_occupancy(const Dims &d);
 int backward_tile_rows(int DH);
 size_t backward_lds(const Dims &d);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
-hipError_t launch_grad(const GradBufs &b, hipStream_t st);
+hipError_t launch_grad(const GradBufs &b, hipStream_t st, const BatchInfo *bi = nullptr);
 void grad_sizes(const Dims &d, int64_t ns, size_t *part_floats);
 int64_t grad_nsp(int64_t ns);
 hipError_t launch_grow(const vmc_model &from, const float *p0, int new_dh, uint64_t seed, double noise,
@@ -41,6 +41,8 @@ hipError_t launch_bump(uint64_t *counter, hipStream_t st);
 hipError_t launch_adam(int64_t n, float *p, const double *g, float *m, float *v, int64_t *t_dev,
                        const vmc_adam_cfg &c, hipStream_t st);
 hipError_t launch_count_nonfinite(const float *x, int64_t n, unsigned long long *count, hipStream_t st);
+hipError_t launch_batch_scan(const BatchInfo &bi, int MT, const int *cnt0, int4 *sched, int *counter,
+                             hipStream_t st);
 
 static const int kMaxN = 1024;
 static const size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
@@ -175,7 +177,9 @@ struct WsMap {
     int64_t nsp;
 };
 
-static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
+// part_floats_min: a batch sizes the weight-gradient partials of every
+// region for the problem that needs the most
+static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns, size_t part_floats_min = 0) {
     WsMap w;
     memset(&w, 0, sizeof(w));
     const size_t es = d.prec == VMC_BF16 ? 2 : 4;
@@ -240,7 +244,7 @@ static WsMap ws_map(const Dims &d, const vmc_ham *H, int64_t ns) {
     w.xT = put((size_t)d.N * 5 * w.nsp * es);
     size_t part_floats = 0;
     grad_sizes(d, ns, &part_floats);
-    w.part = put(part_floats * 4);
+    w.part = put((part_floats > part_floats_min ? part_floats : part_floats_min) * 4);
     w.stats = put(8 * 8);
     w.total = o;
     return w;
@@ -562,6 +566,195 @@ vmc_status vmc_step(const vmc_model *m, const float *params, const vmc_ham *H, i
     if (s != VMC_OK) return s;
     s = grad_from_cache(d, w, ws, ns, configs, eloc, NULL, grad, stats, st);
     if (s != VMC_OK || !counter_dev) return s;
+    return hip_status(launch_bump(counter_dev, st));
+}
+
+// ------------------------------------------------------- batched problems
+// Layout of a batch workspace: one region per problem with the layout of
+// the longest chain, at `pitch` bytes, then the chain-tile queue (int4
+// entries) and its tile counter.
+struct BatchMap {
+    WsMap w;
+    size_t pitch, sched, counter, total;
+    int Nmax, E;
+};
+
+static vmc_status batch_check(int32_t nprob, const vmc_model *m, const int32_t *chain_len, const vmc_ham *H,
+                              int64_t ns, BatchMap *bm) {
+    if (nprob < 1 || nprob > kMaxBatch || !m || !chain_len || !H || ns < 1) return VMC_EINVAL;
+    if (m->dims != 1) return VMC_EUNSUPPORTED;
+    if (ns >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
+    int Nmax = 0, E = 0;
+    size_t part_max = 0;
+    for (int k = 0; k < nprob; k++) {
+        vmc_model mk = *m;
+        mk.Lx = chain_len[k];
+        mk.Ly = 1;
+        if (!valid_model(&mk)) return VMC_EINVAL;
+        if (H[k].kind != H[0].kind) return VMC_EINVAL;
+        const vmc_status hs = check_ham(&mk, &H[k]);
+        if (hs != VMC_OK) return hs;
+        if (padded_dh(mk.d_h) < 0) return VMC_EUNSUPPORTED;
+        const Dims dk = make_dims(&mk);
+        if (!lds_fits(dk)) return VMC_EUNSUPPORTED;
+        if (list_kind(&H[k]) && ns * conn_count(H[k].kind, dk.Lx, 1) >= ((int64_t)1 << 31)) return VMC_EUNSUPPORTED;
+        size_t pf = 0;
+        grad_sizes(dk, ns, &pf);
+        part_max = pf > part_max ? pf : part_max;
+        Nmax = chain_len[k] > Nmax ? chain_len[k] : Nmax;
+        E += chain_len[k] - 1;
+    }
+    vmc_model mm = *m;
+    mm.Lx = Nmax;
+    mm.Ly = 1;
+    const Dims dmax = make_dims(&mm);
+    bm->w = ws_map(dmax, &H[0], ns, part_max);
+    bm->pitch = al(bm->w.total);
+    bm->sched = bm->pitch * nprob;
+    bm->counter = bm->sched + al((size_t)(E + 1) * 16);
+    bm->total = bm->counter + 256;
+    bm->Nmax = Nmax;
+    bm->E = E;
+    return VMC_OK;
+}
+
+vmc_status vmc_batched_workspace_size(int32_t nprob, const vmc_model *m, const int32_t *chain_len, const vmc_ham *H,
+                                      int64_t ns, size_t *bytes) {
+    if (!bytes) return VMC_EINVAL;
+    BatchMap bm;
+    const vmc_status s = batch_check(nprob, m, chain_len, H, ns, &bm);
+    if (s != VMC_OK) return s;
+    *bytes = bm.total;
+    return VMC_OK;
+}
+
+vmc_status vmc_step_batched(int32_t nprob, const vmc_model *m, const int32_t *chain_len, const vmc_ham *H,
+                            const float *params, int64_t ns, uint64_t seed, uint64_t counter, uint64_t *counter_dev,
+                            uint8_t *configs, float *logp, float *phase, double *eloc, double *grad, double *stats,
+                            void *ws, size_t ws_bytes, void *stream) {
+    BatchMap bm;
+    vmc_status s = batch_check(nprob, m, chain_len, H, ns, &bm);
+    if (s != VMC_OK) return s;
+    if (!params || !configs || !logp || !eloc || !grad || !stats || !ws) return VMC_EINVAL;
+    if (((uintptr_t)ws & 255) != 0) return VMC_EINVAL;
+    if (ws_bytes < bm.total) return VMC_ENOSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const WsMap &w = bm.w;
+    vmc_model mm = *m;
+    mm.Lx = bm.Nmax;
+    mm.Ly = 1;
+    const Dims dmax = make_dims(&mm);
+    const int64_t P = param_layout(1, m->d_h, m->glu, m->is_complex).total;
+    BatchInfo bi;
+    memset(&bi, 0, sizeof(bi));
+    bi.n = nprob;
+    bi.tiles = w.fwd_grid;
+    bi.pitch_ws = (int64_t)bm.pitch;
+    bi.pitch_cfg = ns * bm.Nmax;
+    bi.pitch_p = P;
+    bi.ns = ns;
+    bi.sched = at<int4>(ws, bm.sched);
+    bi.nsched = bm.E;
+    for (int k = 0; k < nprob; k++) bi.N[k] = chain_len[k];
+    // 1. staged weights and position table of every problem
+    for (int k = 0; k < nprob; k++) {
+        vmc_model mk = mm;
+        mk.Lx = chain_len[k];
+        const Dims dk = make_dims(&mk);
+        if (stage(dk, params + (size_t)k * P, (char *)ws + (size_t)k * bm.pitch, w, st) != hipSuccess)
+            return VMC_EDEVICE;
+    }
+    // 2. sampling of every problem in one launch (problem k: Philox key seed + k)
+    FwdArgs a = base_args(dmax, ws, w, ns);
+    a.seed = seed;
+    a.counter = counter;
+    a.counter_dev = counter_dev;
+    a.cfg_out = configs;
+    a.cfg_in = configs;
+    a.logp = logp;
+    a.phase = dmax.cplx ? phase : NULL;
+    a.hcache = at<float>(ws, w.hcache);
+    a.lpc = at<float>(ws, w.lpc);
+    a.phc = at<float>(ws, w.phc);
+    a.pre = at<double2>(ws, w.pre);
+    a.act = at<void>(ws, w.act);
+    a.lgT = at<float>(ws, w.lgT);
+    a.hT = at<void>(ws, w.hT);
+    a.gT = at<void>(ws, w.gT);
+    a.nsp = w.nsp;
+    if (phase && !dmax.cplx && launch_fill(phase, (int64_t)nprob * ns, 0.0f, st) != hipSuccess) return VMC_EDEVICE;
+    if (launch_forward(a, MODE_SAMPLE, 1, 1, 1, nprob * w.fwd_grid, st, &bi) != hipSuccess) return VMC_EDEVICE;
+    // 3. connection schedule of every problem, then one queue over all chain tiles
+    const int ek = engine_kind(&H[0]);
+    const int MTc = chain_tile_rows(dmax);
+    for (int k = 0; k < nprob; k++) {
+        char *r = (char *)ws + (size_t)k * bm.pitch;
+        if (launch_sched(ek, chain_len[k], 1, ns, configs + (size_t)k * bi.pitch_cfg, at<int>(r, w.cnt),
+                         at<int>(r, w.list_off), at<int>(r, w.list), at<int>(r, w.tile_start),
+                         at<int>(r, w.tile_counter), MTc, st) != hipSuccess)
+            return VMC_EDEVICE;
+    }
+    if (launch_batch_scan(bi, MTc, at<int>(ws, w.cnt), at<int4>(ws, bm.sched), at<int>(ws, bm.counter), st) !=
+        hipSuccess)
+        return VMC_EDEVICE;
+    // 4. every connected configuration of every sample of every problem in one persistent launch
+    FwdArgs c = base_args(dmax, ws, w, ns);
+    c.cfg_in = configs;
+    c.hcache = at<float>(ws, w.hcache);
+    c.lpc = at<float>(ws, w.lpc);
+    c.phc = at<float>(ws, w.phc);
+    c.pre = at<double2>(ws, w.pre);
+    c.ham_kind = ek;
+    c.cnt = at<int>(ws, w.cnt);
+    c.tile_start = at<int>(ws, w.tile_start);
+    c.list_off = at<int>(ws, w.list_off);
+    c.list = at<int>(ws, w.list);
+    c.tile_counter = at<int>(ws, bm.counter);
+    c.dsuf = at<double2>(ws, w.dsuf);
+    const bool timed = g_timing.enabled && g_timing.n < ChainTiming::kMax;
+    if (timed && hipEventRecord(g_timing.ev[2 * g_timing.n], st) != hipSuccess) return VMC_EDEVICE;
+    if (launch_forward(c, MODE_CHAIN, 0, 0, 0, w.chain_grid, st, &bi) != hipSuccess) return VMC_EDEVICE;
+    if (timed) {
+        if (hipEventRecord(g_timing.ev[2 * g_timing.n + 1], st) != hipSuccess) return VMC_EDEVICE;
+        g_timing.n++;
+    }
+    // 5. local energies of every problem
+    for (int k = 0; k < nprob; k++) {
+        char *r = (char *)ws + (size_t)k * bm.pitch;
+        const int NCk = list_kind(&H[k]) ? conn_count(H[k].kind, chain_len[k], 1) : chain_len[k];
+        if (launch_assemble(H[k], dmax.cplx, chain_len[k], 1, ns, configs + (size_t)k * bi.pitch_cfg,
+                            at<float>(r, w.lpc), at<float>(r, w.phc), at<double2>(r, w.pre), at<double2>(r, w.dsuf),
+                            NCk, eloc + (size_t)k * 2 * ns, st) != hipSuccess)
+            return VMC_EDEVICE;
+    }
+    // 6. statistics and gradient of every problem (batched launches)
+    GradBufs b;
+    b.d = dmax;
+    b.BcT = at<void>(ws, w.BcT);
+    b.BgT = at<void>(ws, w.BgT);
+    b.E = at<float>(ws, w.E);
+    b.Hd = at<float>(ws, w.Hd);
+    b.ns = ns;
+    b.cfg = configs;
+    b.hcache = at<float>(ws, w.hcache);
+    b.act = at<void>(ws, w.act);
+    b.lgT = at<float>(ws, w.lgT);
+    b.eloc = eloc;
+    b.weights = NULL;
+    b.coef_lp = NULL;
+    b.coef_ph = NULL;
+    b.stats = stats;
+    b.dtc = at<void>(ws, w.dtc);
+    b.dtg = at<void>(ws, w.dtg);
+    b.dth = at<void>(ws, w.dth);
+    b.hT = at<void>(ws, w.hT);
+    b.gT = at<void>(ws, w.gT);
+    b.dcol = at<void>(ws, w.dcol);
+    b.xT = at<void>(ws, w.xT);
+    b.part = at<float>(ws, w.part);
+    b.grad = grad;
+    if (launch_grad(b, st, &bi) != hipSuccess) return VMC_EDEVICE;
+    if (!counter_dev) return VMC_OK;
     return hip_status(launch_bump(counter_dev, st));
 }
 

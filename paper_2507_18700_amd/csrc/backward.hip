@@ -39,6 +39,27 @@ struct BwdArgs {
     float *dcol;            // [grid][Lx][MT][DH]
 };
 
+// Arguments of the reverse sweep for problem k of a batch (see BatchInfo):
+// workspace arrays of region k, the caller's configurations, local energies
+// and statistics of problem k.
+__device__ inline void rebase_bwd(BwdArgs &a, const BatchInfo &b, int k) {
+    const int64_t o = (int64_t)k * b.pitch_ws;
+    a.BcT = shift_bytes(a.BcT, o);
+    a.BgT = shift_bytes(a.BgT, o);
+    a.Hd = shift_bytes(a.Hd, o);
+    a.act = shift_bytes(a.act, o);
+    a.lgT = shift_bytes(a.lgT, o);
+    a.hcache = shift_bytes(a.hcache, o);
+    a.dtc = shift_bytes(a.dtc, o);
+    a.dtg = shift_bytes(a.dtg, o);
+    a.dth = shift_bytes(a.dth, o);
+    a.dcol = shift_bytes(a.dcol, o);
+    a.cfg = shift_bytes(a.cfg, (int64_t)k * b.pitch_cfg);
+    a.eloc = shift_bytes(a.eloc, (int64_t)k * b.ns * 16);
+    a.stats = shift_bytes(a.stats, (int64_t)k * 32);
+    a.d.N = a.d.Lx = b.N[k];
+}
+
 // Rows per tile and waves per workgroup.  From d_h = 128 on, 8 waves (one or
 // two 16-unit blocks per wave) hold the transposed weights; one such
 // workgroup fills a compute unit, so the tile is sized to spread the usual
@@ -64,8 +85,8 @@ struct BwdCfg {
     static constexpr int D_LD = NCP + PADE;         // shared row stride of the GLU and cell delta tiles
 };
 
-template <class P, int DIMS, int DH, int NW, int REGW>
-__global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
+template <class P, int DIMS, int DH, int NW, int REGW, int BATCH = 0>
+__global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a0, BatchInfo bi) {
     typedef BwdCfg<P, DIMS, DH, NW> C;
     typedef typename P::store_t T;
     constexpr int MT = C::MT, RB = C::RB, UB = C::UB, VEC = P::VEC, KS = C::KS;
@@ -88,12 +109,20 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w / C::WU, wu = w % C::WU;
     const int l16 = lane & 15, lq = lane >> 4;
+    // batched: one problem per group of bi.tiles work-groups
+    BwdArgs a = a0;
+    int tile = blockIdx.x;
+    if (BATCH) {
+        const int k = blockIdx.x / bi.tiles;
+        tile = blockIdx.x - k * bi.tiles;
+        rebase_bwd(a, bi, k);
+    }
     const int N = a.d.N, Lx = a.d.Lx, Ly = a.d.Ly;
     const int cplx = a.d.cplx, glu = a.d.glu;
     const int64_t ns = a.ns, nsp = a.nsp;
     const T *__restrict__ BcT = (const T *)a.BcT;
     const T *__restrict__ BgT = (const T *)a.BgT;
-    float *dcol = a.dcol + (int64_t)blockIdx.x * Lx * MT * DH;
+    float *dcol = a.dcol + (int64_t)tile * Lx * MT * DH;
 
     // head weights of this lane's units
     float hw[4][UB];
@@ -118,7 +147,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a) {
             }
     }
 
-    const int64_t e0 = (int64_t)blockIdx.x * MT;
+    const int64_t e0 = (int64_t)tile * MT;
     const int nrow = (int)min((int64_t)MT, ns - e0);
     if (tid < MT) {
         const int s = tid < nrow ? (int)(e0 + tid) : -1;
@@ -471,29 +500,41 @@ struct BwdPick {
     static constexpr int NW = BWD_NW(DH);
 };
 
-template <class P, int DIMS, int DH>
-static hipError_t launch_bwd_t(const BwdArgs &a, hipStream_t st) {
+template <class P, int DIMS, int DH, int BATCH>
+static hipError_t launch_bwd_b(const BwdArgs &a, BatchInfo bi, hipStream_t st) {
     constexpr int NW = BwdPick<P, DH>::NW, REGW = BwdPick<P, DH>::REGW;
     typedef BwdCfg<P, DIMS, DH, NW> C;
-    // every column below nsp gets written (zeros past ns)
-    const int grid = (int)((a.nsp + C::MT - 1) / C::MT);
+    // every column below nsp gets written (zeros past ns); batched: that many
+    // tiles per problem (a.d.N is then the longest chain)
+    const int tiles = (int)((a.nsp + C::MT - 1) / C::MT);
+    bi.tiles = tiles;
+    const int grid = BATCH ? bi.n * tiles : tiles;
     size_t dyn = ((size_t)C::MT * a.d.N + 15) / 16 * 16;
     if (REGW) dyn += (size_t)DH * (2 * DH + C::PADE) * sizeof(typename P::store_t);
-    hipError_t e = hipFuncSetAttribute((const void *)rnn_bwd<P, DIMS, DH, NW, REGW>,
+    hipError_t e = hipFuncSetAttribute((const void *)rnn_bwd<P, DIMS, DH, NW, REGW, BATCH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rnn_bwd<P, DIMS, DH, NW, REGW>), dim3(grid), dim3(NW * 64), dyn, st, a);
+    hipLaunchKernelGGL((rnn_bwd<P, DIMS, DH, NW, REGW, BATCH>), dim3(grid), dim3(NW * 64), dyn, st, a, bi);
     return hipGetLastError();
 }
 
+template <class P, int DIMS, int DH>
+static hipError_t launch_bwd_t(const BwdArgs &a, const BatchInfo &bi, hipStream_t st) {
+    if constexpr (DIMS == 1) {
+        if (bi.n > 0) return launch_bwd_b<P, DIMS, DH, 1>(a, bi, st);
+    }
+    if (bi.n > 0) return hipErrorInvalidValue;
+    return launch_bwd_b<P, DIMS, DH, 0>(a, bi, st);
+}
+
 template <class P, int DIMS>
-static hipError_t launch_bwd_d(const BwdArgs &a, hipStream_t st) {
+static hipError_t launch_bwd_d(const BwdArgs &a, const BatchInfo &bi, hipStream_t st) {
     switch (a.d.DH) {
-        case 16: return launch_bwd_t<P, DIMS, 16>(a, st);
-        case 32: return launch_bwd_t<P, DIMS, 32>(a, st);
-        case 64: return launch_bwd_t<P, DIMS, 64>(a, st);
-        case 128: return launch_bwd_t<P, DIMS, 128>(a, st);
-        case 256: return launch_bwd_t<P, DIMS, 256>(a, st);
+        case 16: return launch_bwd_t<P, DIMS, 16>(a, bi, st);
+        case 32: return launch_bwd_t<P, DIMS, 32>(a, bi, st);
+        case 64: return launch_bwd_t<P, DIMS, 64>(a, bi, st);
+        case 128: return launch_bwd_t<P, DIMS, 128>(a, bi, st);
+        case 256: return launch_bwd_t<P, DIMS, 256>(a, bi, st);
     }
     return hipErrorInvalidValue;
 }
@@ -528,7 +569,12 @@ size_t backward_lds(const Dims &d) {
     return d.dims == 1 ? bwd_lds_d<F32, 1>(d.DH, d.N) : bwd_lds_d<F32, 2>(d.DH, d.N);
 }
 
-hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st) {
+// bi: NULL, or the batch of vmc_step_batched (b then describes problem 0
+// with the longest chain's sizes)
+hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st, const BatchInfo *bi) {
+    BatchInfo none;
+    none.n = 0;
+    const BatchInfo &B = bi ? *bi : none;
     BwdArgs a;
     a.d = b.d;
     a.BcT = b.BcT;
@@ -549,8 +595,8 @@ hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st) {
     a.dtg = b.dtg;
     a.dth = b.dth;
     a.dcol = (float *)b.dcol;
-    if (b.d.prec == VMC_BF16) return b.d.dims == 1 ? launch_bwd_d<BF16, 1>(a, st) : launch_bwd_d<BF16, 2>(a, st);
-    return b.d.dims == 1 ? launch_bwd_d<F32, 1>(a, st) : launch_bwd_d<F32, 2>(a, st);
+    if (b.d.prec == VMC_BF16) return b.d.dims == 1 ? launch_bwd_d<BF16, 1>(a, B, st) : launch_bwd_d<BF16, 2>(a, B, st);
+    return b.d.dims == 1 ? launch_bwd_d<F32, 1>(a, B, st) : launch_bwd_d<F32, 2>(a, B, st);
 }
 
 }  // namespace vmc

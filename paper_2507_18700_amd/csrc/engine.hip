@@ -4,10 +4,14 @@
 
 namespace vmc {
 
-hipError_t launch_engine_bf16_1d(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st);
-hipError_t launch_engine_bf16_2d(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st);
-hipError_t launch_engine_f32_1d(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st);
-hipError_t launch_engine_f32_2d(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st);
+hipError_t launch_engine_bf16_1d(const FwdArgs &a, const BatchInfo &bi, int mode, int sh, int sl, int sa, int grid,
+                              hipStream_t st);
+hipError_t launch_engine_bf16_2d(const FwdArgs &a, const BatchInfo &bi, int mode, int sh, int sl, int sa, int grid,
+                              hipStream_t st);
+hipError_t launch_engine_f32_1d(const FwdArgs &a, const BatchInfo &bi, int mode, int sh, int sl, int sa, int grid,
+                              hipStream_t st);
+hipError_t launch_engine_f32_2d(const FwdArgs &a, const BatchInfo &bi, int mode, int sh, int sl, int sa, int grid,
+                              hipStream_t st);
 
 int chain_occupancy_bf16_1d(int DH, int N);
 int chain_occupancy_bf16_2d(int DH, int N);
@@ -21,13 +25,18 @@ int chain_occupancy(const Dims &d) {
     return d.dims == 1 ? chain_occupancy_f32_1d(d.DH, d.N) : chain_occupancy_f32_2d(d.DH, d.N);
 }
 
+// bi: NULL, or the batch of vmc_step_batched (1D chain and sampling launches)
 hipError_t launch_forward(const FwdArgs &a, int mode, int store_h, int store_lpc, int store_act, int grid,
-                          hipStream_t st) {
+                          hipStream_t st, const BatchInfo *bi) {
+    BatchInfo none;
+    none.n = 0;
+    const BatchInfo &b = bi ? *bi : none;
+    if (b.n > 0 && a.d.dims != 1) return hipErrorInvalidValue;
     if (a.d.prec == VMC_BF16)
-        return a.d.dims == 1 ? launch_engine_bf16_1d(a, mode, store_h, store_lpc, store_act, grid, st)
-                             : launch_engine_bf16_2d(a, mode, store_h, store_lpc, store_act, grid, st);
-    return a.d.dims == 1 ? launch_engine_f32_1d(a, mode, store_h, store_lpc, store_act, grid, st)
-                         : launch_engine_f32_2d(a, mode, store_h, store_lpc, store_act, grid, st);
+        return a.d.dims == 1 ? launch_engine_bf16_1d(a, b, mode, store_h, store_lpc, store_act, grid, st)
+                             : launch_engine_bf16_2d(a, b, mode, store_h, store_lpc, store_act, grid, st);
+    return a.d.dims == 1 ? launch_engine_f32_1d(a, b, mode, store_h, store_lpc, store_act, grid, st)
+                         : launch_engine_f32_2d(a, b, mode, store_h, store_lpc, store_act, grid, st);
 }
 
 // Rows per tile of tile class tc (0, 1 or 2, see Eng) for this model.

@@ -139,9 +139,9 @@ struct PosInfo {
 // CPX: the complex (phase) head fixed at compile time (0 or 1) or read at run
 // time (-1).  The chain launch is instantiated for both values: without the
 // run-time branches its epilogue basic blocks are larger and better scheduled.
-template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF, int TC, int CPX = -1>
-__global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int store_h_, int store_lpc_,
-                                                      int store_act_) {
+template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF, int TC, int CPX = -1, int BATCH = 0>
+__global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, int mode, int store_h_,
+                                                      int store_lpc_, int store_act_) {
     // cache writes exist only in the STORE variant (the chain kernel has none)
     const int store_h = STORE && store_h_, store_lpc = STORE && store_lpc_, store_act = STORE && store_act_;
     // the launch mode is fixed by the instantiation: the chain tile class runs
@@ -176,43 +176,114 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w / C::WU, wu = w % C::WU;
-    const int N = a.d.N, Lx = a.d.Lx, Ly = a.d.Ly;
+    // the arguments of this work-group's problem (a batched row launch: one
+    // problem per group of `bi.tiles` work-groups; the batched chain launch
+    // rebases per tile)
+    FwdArgs a = a0;
+    int row_tile = blockIdx.x;
+    if (BATCH && !CHAIN) {
+        const int k = blockIdx.x / bi.tiles;
+        row_tile = blockIdx.x - k * bi.tiles;
+        rebase_fwd(a, bi, k);
+    }
     const int cplx = CPX >= 0 ? CPX : a.d.cplx, glu = a.d.glu;
-    const T *__restrict__ Bc = (const T *)a.Bc;
-    const T *__restrict__ Bg = (const T *)a.Bg;
-    const T *__restrict__ hcs = (const T *)a.hcs;
-    const int4 *__restrict__ postab = a.postab;
     const int64_t ns_c = a.ns_cache;
-    T *colbuf = (T *)a.colbuf + (int64_t)blockIdx.x * Lx * MT * DH;
     const int l16 = lane & 15, lq = lane >> 4;
     auto unit0 = [&](int ub) __attribute__((always_inline)) { return wu * C::UW + ub * 16 + 4 * lq; };
 
-    // per-lane constants of this lane's units: GLU biases, amplitude head
+    // per-problem state, set by setup(): sizes, weight pointers, the per-lane
+    // constants of this lane's units (GLU biases, amplitude head), the
+    // register-resident weights and the LDS tables
+    int N, Lx, Ly;
+    const T *__restrict__ Bc;
+    const T *__restrict__ Bg;
+    const T *__restrict__ hcs;
+    const int4 *__restrict__ postab;
+    T *colbuf;
     float gb1[UB][4], gb2[UB][4], hw0[UB][4], hw1[UB][4];
     float bin_[DIMS == 1 ? UB : 1][4], win0[DIMS == 1 ? UB : 1][4], win1[DIMS == 1 ? UB : 1][4];
+    float hc0, hc1, hc2, hc3;
+    // REGW: cell and GLU weight fragments in registers for the whole launch
+    // (the hidden k-steps; the indicator columns come from the input table)
+    i32x4_t wreg[REGW ? 3 : 1][REGW ? NKS - 1 : 1][REGW ? UB : 1];
+    uint4 wgl[REGW ? 2 : 1][REGW ? NKG : 1][REGW ? UB : 1];
+    auto setup = [&]() __attribute__((always_inline)) {
+        N = a.d.N;
+        Lx = a.d.Lx;
+        Ly = a.d.Ly;
+        Bc = (const T *)a.Bc;
+        Bg = (const T *)a.Bg;
+        hcs = (const T *)a.hcs;
+        postab = a.postab;
+        colbuf = (T *)a.colbuf + (int64_t)blockIdx.x * Lx * MT * DH;
 #pragma unroll
-    for (int ub = 0; ub < UB; ub++)
+        for (int ub = 0; ub < UB; ub++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int u = unit0(ub) + i;
-            if (!CL) {
-                gb1[ub][i] = a.E[E_B1 * DH + u];
-                gb2[ub][i] = a.E[E_B2 * DH + u];
-                hw0[ub][i] = a.Hd[u];
-                hw1[ub][i] = a.Hd[DH + u];
+            for (int i = 0; i < 4; i++) {
+                const int u = unit0(ub) + i;
+                if (!CL) {
+                    gb1[ub][i] = a.E[E_B1 * DH + u];
+                    gb2[ub][i] = a.E[E_B2 * DH + u];
+                    hw0[ub][i] = a.Hd[u];
+                    hw1[ub][i] = a.Hd[DH + u];
+                }
+                if (DIMS == 1) {
+                    bin_[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_BIN * DH + u];
+                    win0[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_XIN0 * DH + u];
+                    win1[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_XIN1 * DH + u];
+                }
             }
-            if (DIMS == 1) {
-                bin_[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_BIN * DH + u];
-                win0[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_XIN0 * DH + u];
-                win1[ub % (DIMS == 1 ? UB : 1)][i] = a.E[E1_XIN1 * DH + u];
+        for (int e = tid; e < 2 * DH; e += NT) (&sHw[0][0])[e] = a.Hd[2 * DH + e];
+        if (CL)
+            for (int e = tid; e < 4 * DH; e += NT) {
+                const int k = e / DH, u = e - k * DH;
+                sCst[CL ? k : 0][CL ? u : 0] = k == 0 ? a.E[E_B1 * DH + u] : k == 1 ? a.E[E_B2 * DH + u] : a.Hd[(k - 2) * DH + u];
             }
+        hc0 = a.hc[0];
+        hc1 = a.hc[1];
+        hc2 = a.hc[2];
+        hc3 = a.hc[3];
+        if (REGW) {
+#pragma unroll
+            for (int g = 0; g < 3; g++)
+#pragma unroll
+                for (int ks = 0; ks < NKS - 1; ks++)
+#pragma unroll
+                    for (int ub = 0; ub < UB; ub++) {
+                        const int n = g * DH + wu * C::UW + ub * 16 + l16;
+                        wreg[g][ks][ub] = *(const i32x4_t *)&Bc[(int64_t)n * KPX + ks * KS + VEC * lq];
+                    }
+#pragma unroll
+            for (int g = 0; g < 2; g++)
+#pragma unroll
+                for (int kq = 0; kq < NKG; kq++)
+#pragma unroll
+                    for (int ub = 0; ub < UB; ub++) {
+                        const int n = g * DH + wu * C::UW + ub * 16 + l16;
+                        wgl[g][kq][ub] = *(const uint4 *)&Bg[(int64_t)n * KHB + kq * KS + VEC * lq];
+                    }
         }
-    for (int e = tid; e < 2 * DH; e += NT) (&sHw[0][0])[e] = a.Hd[2 * DH + e];
-    if (CL)
-        for (int e = tid; e < 4 * DH; e += NT) {
-            const int k = e / DH, u = e - k * DH;
-            sCst[CL ? k : 0][CL ? u : 0] = k == 0 ? a.E[E_B1 * DH + u] : k == 1 ? a.E[E_B2 * DH + u] : a.Hd[(k - 2) * DH + u];
-        }
+        if (XT)
+            for (int e = tid; e < C::NXG * C::NXC * DH; e += NT) {
+                const int g = e / (C::NXC * DH), r = e - g * (C::NXC * DH), cls = r / DH, u = r - cls * DH;
+                const int xz = cls % 3 - 1, xv = cls / 3 - 1;
+                float v;
+                if (DIMS == 1) {
+                    // gates u, r: bias + one-hot weight of x_{n-1}; gate m: its bias only
+                    const float *e1 = a.E + (int64_t)(3 * g) * DH + u;
+                    v = e1[0];
+                    if (g < 2) v += xz == 0 ? e1[DH] : xz == 1 ? e1[2 * DH] : 0.f;
+                } else {
+                    // gates c, u: bias + one-hot weights of the horizontal and vertical inputs
+                    const float *e2 = a.E + (int64_t)(5 * g) * DH + u;
+                    v = e2[0];
+                    v += xz == 0 ? e2[DH] : xz == 1 ? e2[2 * DH] : 0.f;
+                    v += xv == 0 ? e2[3 * DH] : xv == 1 ? e2[4 * DH] : 0.f;
+                }
+                sXt[XT ? g : 0][XT ? cls : 0][XT ? u : 0] = v;
+            }
+    };
+    if (!(BATCH && CHAIN)) setup();
     // constant k (0: GLU bias 1, 1: GLU bias 2, 2, 3: amplitude-head rows) of the lane's 4 units of block ub
     auto cst4 = [&](int k, int ub, float *v) __attribute__((always_inline)) {
         if (CL) {
@@ -227,34 +298,8 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
         }
     };
     for (int e = tid; e < C::NLOG * C::WU * MT * 4; e += NT) (&sLog[0][0][0][0])[e] = 0.f;
-    const float hc0 = a.hc[0], hc1 = a.hc[1], hc2 = a.hc[2], hc3 = a.hc[3];
     // Philox counter of the sampling decisions: given, or read once from device memory
     const uint64_t ctr = (!TF && a.counter_dev) ? *kconst(a.counter_dev) : a.counter;
-
-    // REGW: cell and GLU weight fragments in registers for the whole launch
-    // (the hidden k-steps; the indicator columns come from the input table)
-    i32x4_t wreg[REGW ? 3 : 1][REGW ? NKS - 1 : 1][REGW ? UB : 1];
-    uint4 wgl[REGW ? 2 : 1][REGW ? NKG : 1][REGW ? UB : 1];
-    if (REGW) {
-#pragma unroll
-        for (int g = 0; g < 3; g++)
-#pragma unroll
-            for (int ks = 0; ks < NKS - 1; ks++)
-#pragma unroll
-                for (int ub = 0; ub < UB; ub++) {
-                    const int n = g * DH + wu * C::UW + ub * 16 + l16;
-                    wreg[g][ks][ub] = *(const i32x4_t *)&Bc[(int64_t)n * KPX + ks * KS + VEC * lq];
-                }
-#pragma unroll
-        for (int g = 0; g < 2; g++)
-#pragma unroll
-            for (int kq = 0; kq < NKG; kq++)
-#pragma unroll
-                for (int ub = 0; ub < UB; ub++) {
-                    const int n = g * DH + wu * C::UW + ub * 16 + l16;
-                    wgl[g][kq][ub] = *(const uint4 *)&Bg[(int64_t)n * KHB + kq * KS + VEC * lq];
-                }
-    }
     // zero the operand tiles once (padding columns stay zero); the bias
     // class of the indicator block is always on
     for (int e = tid; e < 2 * MT * H_LD; e += NT) (&sH[0][0])[e] = cvt<P>(0.f);
@@ -265,25 +310,6 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             const int c = e % X_LD;
             const bool bias_col = VEC == 8 ? (c == 8 || c == 9) : c == 4;
             (&sX[0][0])[e] = cvt<P>(bias_col ? 1.f : 0.f);
-        }
-    if (XT)
-        for (int e = tid; e < C::NXG * C::NXC * DH; e += NT) {
-            const int g = e / (C::NXC * DH), r = e - g * (C::NXC * DH), cls = r / DH, u = r - cls * DH;
-            const int xz = cls % 3 - 1, xv = cls / 3 - 1;
-            float v;
-            if (DIMS == 1) {
-                // gates u, r: bias + one-hot weight of x_{n-1}; gate m: its bias only
-                const float *e1 = a.E + (int64_t)(3 * g) * DH + u;
-                v = e1[0];
-                if (g < 2) v += xz == 0 ? e1[DH] : xz == 1 ? e1[2 * DH] : 0.f;
-            } else {
-                // gates c, u: bias + one-hot weights of the horizontal and vertical inputs
-                const float *e2 = a.E + (int64_t)(5 * g) * DH + u;
-                v = e2[0];
-                v += xz == 0 ? e2[DH] : xz == 1 ? e2[2 * DH] : 0.f;
-                v += xv == 0 ? e2[3 * DH] : xv == 1 ? e2[4 * DH] : 0.f;
-            }
-            sXt[XT ? g : 0][XT ? cls : 0][XT ? u : 0] = v;
         }
 
     auto pos = [&](int qn) -> PosInfo __attribute__((always_inline)) {
@@ -332,11 +358,37 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
     };
 
     bool first = true;
+    int cur_prob = -1;  // batched chain launch: the problem whose state setup() loaded
     for (;;) {
         // ---------------------------------------------------------- tile
         int p = -1, nrow;
         int64_t e0;
-        if (CHAIN) {
+        if (CHAIN && BATCH) {
+            __syncthreads();
+            if (tid == 0) sTile = atomicAdd(a0.tile_counter, 1);
+            __syncthreads();
+            // one queue over the tiles of every problem, longest chains first:
+            // the entry (first tile, problem, position) that holds tile t
+            const int t = __builtin_amdgcn_readfirstlane(sTile);
+            const auto *sc = kconst((const int *)bi.sched);
+            if (t >= sc[4 * bi.nsched]) break;
+            int lo = 0, hi = bi.nsched - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (sc[4 * mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const int k = sc[4 * lo + 1];
+            p = sc[4 * lo + 2];
+            e0 = (int64_t)(t - sc[4 * lo]) * MT;
+            if (k != cur_prob) {
+                a = a0;
+                rebase_fwd(a, bi, k);
+                setup();
+                cur_prob = k;
+            }
+            nrow = (int)min((int64_t)MT, (int64_t)kconst(a.cnt)[p] - e0);
+        } else if (CHAIN) {
             __syncthreads();
             if (tid == 0) sTile = atomicAdd(a.tile_counter, 1);
             __syncthreads();
@@ -356,7 +408,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
             nrow = (int)min((int64_t)MT, (int64_t)kconst(a.cnt)[p] - e0);
         } else {
             if (!first) break;
-            e0 = (int64_t)blockIdx.x * MT;
+            e0 = (int64_t)row_tile * MT;
             nrow = (int)min((int64_t)MT, a.nrows - e0);
         }
         first = false;
@@ -921,38 +973,56 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a, int mode, int s
 
 // ------------------------------------------------------------ launchers
 
-template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF, int TC, int CPX = -1>
-static hipError_t launch_engine_s(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
+template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF, int TC, int CPX = -1, int BATCH = 0>
+static hipError_t launch_engine_s(const FwdArgs &a, const BatchInfo &bi, int mode, int sh, int sl, int sa, int grid,
+                                  hipStream_t st) {
     typedef Eng<P, DIMS, DH, NW, TC> C;
+    // (batched: a.d.N is the longest chain of the batch)
     size_t dyn = ((size_t)C::MT * a.d.N + 15) / 16 * 16;
-    hipError_t e = hipFuncSetAttribute((const void *)rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF, TC, CPX>,
+    hipError_t e = hipFuncSetAttribute((const void *)rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF, TC, CPX, BATCH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF, TC, CPX>), dim3(grid), dim3(NW * 64), dyn, st, a, mode,
-                       sh, sl, sa);
+    hipLaunchKernelGGL((rnn_engine<P, DIMS, DH, NW, REGW, STORE, TF, TC, CPX, BATCH>), dim3(grid), dim3(NW * 64), dyn,
+                       st, a, bi, mode, sh, sl, sa);
     return hipGetLastError();
 }
 
 // row launches of tile class TC (0 or 2)
 template <class P, int DIMS, int DH, int NW, int REGW, int TC>
-static hipError_t launch_engine_r(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
+static hipError_t launch_engine_r(const FwdArgs &a, const BatchInfo &bi, int mode, int sh, int sl, int sa, int grid,
+                                  hipStream_t st) {
     const bool store = sh || sl || sa, tf = mode != MODE_SAMPLE;
+    if constexpr (DIMS == 1) {
+        // batched sampling (the only batched row launch: vmc_step_batched)
+        if (bi.n > 0) {
+            if (tf || !store) return hipErrorInvalidValue;
+            return launch_engine_s<P, DIMS, DH, NW, REGW, 1, 0, TC, -1, 1>(a, bi, mode, sh, sl, sa, grid, st);
+        }
+    }
     if (store)
-        return tf ? launch_engine_s<P, DIMS, DH, NW, REGW, 1, 1, TC>(a, mode, sh, sl, sa, grid, st)
-                  : launch_engine_s<P, DIMS, DH, NW, REGW, 1, 0, TC>(a, mode, sh, sl, sa, grid, st);
-    return tf ? launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, TC>(a, mode, sh, sl, sa, grid, st)
-              : launch_engine_s<P, DIMS, DH, NW, REGW, 0, 0, TC>(a, mode, sh, sl, sa, grid, st);
+        return tf ? launch_engine_s<P, DIMS, DH, NW, REGW, 1, 1, TC>(a, bi, mode, sh, sl, sa, grid, st)
+                  : launch_engine_s<P, DIMS, DH, NW, REGW, 1, 0, TC>(a, bi, mode, sh, sl, sa, grid, st);
+    return tf ? launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, TC>(a, bi, mode, sh, sl, sa, grid, st)
+              : launch_engine_s<P, DIMS, DH, NW, REGW, 0, 0, TC>(a, bi, mode, sh, sl, sa, grid, st);
 }
 
 template <class P, int DIMS, int DH, int NW, int REGW>
-static hipError_t launch_engine_t(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
-    if (mode == MODE_CHAIN)
-        return a.d.cplx ? launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, 1, 1>(a, mode, sh, sl, sa, grid, st)
-                        : launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, 1, 0>(a, mode, sh, sl, sa, grid, st);
-    if constexpr (Eng<P, DIMS, DH, NW, 2>::HAS_ALT) {
-        if (a.d.row_alt) return launch_engine_r<P, DIMS, DH, NW, REGW, 2>(a, mode, sh, sl, sa, grid, st);
+static hipError_t launch_engine_t(const FwdArgs &a, const BatchInfo &bi, int mode, int sh, int sl, int sa, int grid,
+                                  hipStream_t st) {
+    if (mode == MODE_CHAIN) {
+        if constexpr (DIMS == 1) {
+            if (bi.n > 0)
+                return a.d.cplx
+                           ? launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, 1, 1, 1>(a, bi, mode, sh, sl, sa, grid, st)
+                           : launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, 1, 0, 1>(a, bi, mode, sh, sl, sa, grid, st);
+        }
+        return a.d.cplx ? launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, 1, 1>(a, bi, mode, sh, sl, sa, grid, st)
+                        : launch_engine_s<P, DIMS, DH, NW, REGW, 0, 1, 1, 0>(a, bi, mode, sh, sl, sa, grid, st);
     }
-    return launch_engine_r<P, DIMS, DH, NW, REGW, 0>(a, mode, sh, sl, sa, grid, st);
+    if constexpr (Eng<P, DIMS, DH, NW, 2>::HAS_ALT) {
+        if (a.d.row_alt) return launch_engine_r<P, DIMS, DH, NW, REGW, 2>(a, bi, mode, sh, sl, sa, grid, st);
+    }
+    return launch_engine_r<P, DIMS, DH, NW, REGW, 0>(a, bi, mode, sh, sl, sa, grid, st);
 }
 
 // Variant per precision and width: bfloat16 up to d_h = 128 keeps the
@@ -964,9 +1034,10 @@ struct Pick {
 };
 
 template <class P, int DIMS>
-static hipError_t launch_engine_d(const FwdArgs &a, int mode, int sh, int sl, int sa, int grid, hipStream_t st) {
+static hipError_t launch_engine_d(const FwdArgs &a, const BatchInfo &bi, int mode, int sh, int sl, int sa, int grid,
+                                  hipStream_t st) {
 #define VMC_ENG(DHV) \
-    launch_engine_t<P, DIMS, DHV, Pick<P, DHV>::NW, Pick<P, DHV>::REGW>(a, mode, sh, sl, sa, grid, st)
+    launch_engine_t<P, DIMS, DHV, Pick<P, DHV>::NW, Pick<P, DHV>::REGW>(a, bi, mode, sh, sl, sa, grid, st)
     switch (a.d.DH) {
         case 16: return VMC_ENG(16);
         case 32: return VMC_ENG(32);

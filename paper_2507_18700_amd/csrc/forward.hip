@@ -263,6 +263,73 @@ __global__ void tile_scan(int N, int MT, const int *cnt, int *tile_start) {
     }
 }
 
+// One queue over the chain tiles of a batch, longest chains first.  The
+// problems come sorted by decreasing length (Ns[j] = length of problem
+// ord[j]), so the problems whose chains reach length L (first changed
+// position p = N - 1 - L) are a prefix of that order: the entries, one per
+// (L, problem), run L = Lmax..1 and within each L over that prefix.  Entry
+// e = {first tile, problem, p}; sched[E] = {total tiles}; the tile counter
+// of the launch is reset.  One work-group.
+struct BatchSort {
+    int n;
+    int ord[kMaxBatch], Ns[kMaxBatch];
+};
+
+__global__ __launch_bounds__(1024) void batch_scan(BatchSort bs, int MT, int64_t pitch_ws, const int *cnt0,
+                                                   int4 *sched, int *counter, int E) {
+    __shared__ int off[1025];   // first entry of length index i = Lmax - L
+    __shared__ int part[1024];
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int Lmax = bs.Ns[0] - 1;
+    for (int i = tid; i < Lmax; i += NT) {
+        const int L = Lmax - i;
+        int c = 0;
+        while (c < bs.n && bs.Ns[c] - 1 >= L) c++;
+        off[i + 1] = c;  // entries of length L, prefix-summed below
+    }
+    __syncthreads();
+    if (tid == 0) {
+        off[0] = 0;
+        for (int i = 1; i <= Lmax; i++) off[i] += off[i - 1];
+    }
+    __syncthreads();
+    // tile counts of this thread's contiguous range of entries, then a scan
+    const int per = (E + NT - 1) / NT, e0 = tid * per, e1 = min(E, e0 + per);
+    int sum = 0;
+    for (int e = e0; e < e1; e++) {
+        int lo = 0, hi = Lmax - 1;  // largest i with off[i] <= e
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        const int L = Lmax - lo, j = e - off[lo], k = bs.ord[j], p = bs.Ns[j] - 1 - L;
+        const int *cnt = (const int *)((const char *)cnt0 + (int64_t)k * pitch_ws);
+        const int nt = (cnt[p] + MT - 1) / MT;
+        sched[e] = make_int4(nt, k, p, 0);
+        sum += nt;
+    }
+    part[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        int t = 0;
+        for (int i = 0; i < NT; i++) {
+            const int v = part[i];
+            part[i] = t;
+            t += v;
+        }
+        sched[E] = make_int4(t, -1, -1, 0);
+        *counter = 0;
+    }
+    __syncthreads();
+    int t = part[tid];
+    for (int e = e0; e < e1; e++) {
+        const int nt = sched[e].x;
+        sched[e].x = t;
+        t += nt;
+    }
+}
+
 // E_loc assembly (Eqs. 6-9): diagonal part (bonds; all pairs for the
 // long-range TFIM; none for the cluster state), off-diagonal part
 // sum_k coupling * psi(sigma')/psi(sigma), where
@@ -391,6 +458,29 @@ hipError_t launch_sched(int ham_kind, int Lx, int Ly, int64_t ns, const uint8_t 
         hipLaunchKernelGGL(conn_list, dim3(grid), dim3(256), 0, st, ham_kind, cfg, ns, Lx, Ly, cnt, list_off, list);
     }
     hipLaunchKernelGGL(tile_scan, dim3(1), dim3(64), 0, st, Lx * Ly, MT, cnt, tile_start);
+    return hipGetLastError();
+}
+
+// Entries of the batch queue: one per (problem, first changed position)
+// with a chain after it, i.e. sum_k (N_k - 1).
+hipError_t launch_batch_scan(const BatchInfo &bi, int MT, const int *cnt0, int4 *sched, int *counter,
+                             hipStream_t st) {
+    BatchSort bs;
+    bs.n = bi.n;
+    int E = 0;
+    for (int k = 0; k < bi.n; k++) {
+        bs.ord[k] = k;
+        E += bi.N[k] - 1;
+    }
+    for (int a = 1; a < bi.n; a++)  // stable sort by decreasing length
+        for (int b = a; b > 0 && bi.N[bs.ord[b]] > bi.N[bs.ord[b - 1]]; b--) {
+            const int t = bs.ord[b];
+            bs.ord[b] = bs.ord[b - 1];
+            bs.ord[b - 1] = t;
+        }
+    for (int j = 0; j < bi.n; j++) bs.Ns[j] = bi.N[bs.ord[j]];
+    if (E != bi.nsched) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_scan, dim3(1), dim3(1024), 0, st, bs, MT, bi.pitch_ws, cnt0, sched, counter, E);
     return hipGetLastError();
 }
 

@@ -22,11 +22,14 @@ constexpr int DW_NF = 9, DW_COLS = 144;  // input-column fragments / columns per
 // ------------------------------------------------------------- statistics
 
 // One work-group: Ebar = sum w E, var = sum w |E - Ebar|^2, non-finite count.
-// Fixed per-thread strides and a fixed tree: bitwise reproducible.
+// Fixed per-thread strides and a fixed tree: bitwise reproducible.  A batch
+// runs one work-group per problem (blockIdx.y; no weights).
 __global__ __launch_bounds__(1024) void stats_kernel(int64_t ns, const double *eloc, const double *w,
                                                      double *stats) {
     __shared__ double s0[1024], s1[1024], s2[1024];
     const int t = threadIdx.x;
+    eloc += (int64_t)blockIdx.y * 2 * ns;
+    stats += (int64_t)blockIdx.y * 4;
     double er = 0.0, ei = 0.0, bad = 0.0;
     for (int64_t s = t; s < ns; s += 1024) {
         double ws = w ? w[s] : 1.0 / (double)ns;
@@ -71,6 +74,16 @@ __global__ __launch_bounds__(1024) void stats_kernel(int64_t ns, const double *e
 
 // ------------------------------------------------- weight-gradient contraction
 
+// Per-problem shape of the weight-gradient contraction of a batch: regions
+// of the workspace at pitch_ws, chain lengths and the sample chunking of each
+// problem (the same as vmc_step chooses for it alone).
+struct DwBatch {
+    int n;
+    int64_t pitch_ws, pitch_p;
+    int N[kMaxBatch], nchunk[kMaxBatch];
+    int64_t chunk[kMaxBatch];
+};
+
 struct DwArgs {
     Dims d;
     int seg;              // 0 cell, 1 GLU, 2 heads
@@ -114,7 +127,14 @@ __device__ inline int64_t dw_source(const DwArgs &a, int q, int k, bool &extra) 
 // predecessor's spin, the one-hot of the vertical predecessor's spin (zeros
 // where the predecessor is absent), transposed [N][5][nsp].
 template <class P>
-__global__ void build_extras(Dims d, int64_t ns, int64_t nsp, const uint8_t *cfg, typename P::store_t *xT) {
+__global__ void build_extras(Dims d, int64_t ns, int64_t nsp, const uint8_t *cfg, typename P::store_t *xT,
+                             DwBatch gb, int64_t pitch_cfg) {
+    if (gb.n > 0) {  // batch: problem blockIdx.y
+        const int k = blockIdx.y;
+        d.N = d.Lx = gb.N[k];
+        cfg += (int64_t)k * pitch_cfg;
+        xT = shift_bytes(xT, (int64_t)k * gb.pitch_ws);
+    }
     const int N = d.N, Lx = d.Lx;
     const int64_t total = (int64_t)N * nsp;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -138,8 +158,21 @@ __global__ void build_extras(Dims d, int64_t ns, int64_t nsp, const uint8_t *cfg
 // whole work-group stages in LDS (double-buffered), so each input row is read
 // from memory once per row tile instead of once per wave.
 template <class P, int MF>
-__global__ __launch_bounds__(512) void dw_mfma(DwArgs a) {
+__global__ __launch_bounds__(512) void dw_mfma(DwArgs a, DwBatch gb) {
     typedef typename P::store_t T;
+    if (gb.n > 0) {  // batch: problem blockIdx.y, its region and chunking
+        const int k = blockIdx.y;
+        const int64_t o = (int64_t)k * gb.pitch_ws;
+        a.A = shift_bytes(a.A, o);
+        a.hT = shift_bytes(a.hT, o);
+        a.gT = shift_bytes(a.gT, o);
+        a.xT = shift_bytes(a.xT, o);
+        a.part = shift_bytes(a.part, o);
+        a.d.N = a.d.Lx = gb.N[k];
+        a.nchunk = gb.nchunk[k];
+        a.chunk = gb.chunk[k];
+        a.units = a.d.N * a.nchunk;
+    }
     constexpr int VEC = P::VEC, KS = P::KSTEP;
     constexpr int LDB = KS + 16 / (int)sizeof(T);  // padded row of the staged input tile
     constexpr int CPR = KS / VEC;                  // 16-byte chunks per staged row
@@ -315,8 +348,14 @@ __device__ inline int64_t dw_param(const Dims &d, int seg, int m, int k) {
 // row: 8 groups of 32 threads take every 8th partial (4 loads in flight per
 // thread), then the 8 group sums are added in a fixed order.
 __global__ __launch_bounds__(256) void dw_reduce(Dims d, int seg, const float *part, int Q, int Mp, int Kp, int K,
-                                                 int MD, double *grad) {
+                                                 int MD, double *grad, DwBatch gb) {
     __shared__ double sg[8][32];
+    if (gb.n > 0) {  // batch: problem blockIdx.y
+        const int kk = blockIdx.y;
+        part = shift_bytes(part, (int64_t)kk * gb.pitch_ws);
+        grad += (int64_t)kk * gb.pitch_p;
+        Q = gb.N[kk] * gb.nchunk[kk];
+    }
     const int W = K + 5, nkb = (W + 31) / 32;
     const int m = blockIdx.x / nkb, k = (blockIdx.x % nkb) * 32 + (threadIdx.x & 31), g = threadIdx.x >> 5;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -410,33 +449,62 @@ void grad_sizes(const Dims &d, int64_t ns, size_t *part_floats) {
 }
 
 template <class P>
-static void launch_dw_p(const DwArgs &a, const SegDims &sd, hipStream_t st) {
-    const dim3 grid(kXcds * ((a.units + kXcds - 1) / kXcds) * a.tiles);
+static void launch_dw_p(const DwArgs &a, const SegDims &sd, const DwBatch &gb, int units_max, hipStream_t st) {
+    const dim3 grid(kXcds * ((units_max + kXcds - 1) / kXcds) * a.tiles, gb.n > 0 ? gb.n : 1);
     switch (dw_mf(sd.MD)) {
-        case 1: hipLaunchKernelGGL((dw_mfma<P, 1>), grid, dim3(512), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((dw_mfma<P, 2>), grid, dim3(512), 0, st, a); break;
-        default: hipLaunchKernelGGL((dw_mfma<P, 3>), grid, dim3(512), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((dw_mfma<P, 1>), grid, dim3(512), 0, st, a, gb); break;
+        case 2: hipLaunchKernelGGL((dw_mfma<P, 2>), grid, dim3(512), 0, st, a, gb); break;
+        default: hipLaunchKernelGGL((dw_mfma<P, 3>), grid, dim3(512), 0, st, a, gb); break;
     }
 }
 
-hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st);
+hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st, const BatchInfo *bi);
 
-hipError_t launch_grad(const GradBufs &b, hipStream_t st) {
+// bi: NULL, or the batch of vmc_step_batched; b then describes problem 0 with
+// the longest chain's sizes (grad and stats of problem k at k * pitch_p and
+// k * 4, local energies at k * 2 ns).
+hipError_t launch_grad(const GradBufs &b, hipStream_t st, const BatchInfo *bi) {
     const Dims &d = b.d;
-    if (!b.coef_lp) hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(1024), 0, st, b.ns, b.eloc, b.weights, b.stats);
-    hipError_t e = launch_backward(b, grad_nsp(b.ns), st);
+    const int nb = bi ? bi->n : 0;
+    if (nb > 0 && (b.coef_lp || b.weights)) return hipErrorInvalidValue;
+    if (!b.coef_lp)
+        hipLaunchKernelGGL(stats_kernel, dim3(1, nb > 0 ? nb : 1), dim3(1024), 0, st, b.ns, b.eloc, b.weights,
+                           b.stats);
+    hipError_t e = launch_backward(b, grad_nsp(b.ns), st, bi);
     if (e != hipSuccess) return e;
+    const int64_t nsp = grad_nsp(b.ns);
+    // per-problem chunking of the weight-gradient contraction (as vmc_step alone)
+    DwBatch gbs[3];
+    for (int seg = 0; seg < 3; seg++) {
+        gbs[seg].n = nb;
+        if (nb == 0) continue;
+        gbs[seg].pitch_ws = bi->pitch_ws;
+        gbs[seg].pitch_p = bi->pitch_p;
+        for (int k = 0; k < nb; k++) {
+            Dims dk = d;
+            dk.N = dk.Lx = bi->N[k];
+            const SegDims sk = seg_dims(dk, seg);
+            gbs[seg].N[k] = bi->N[k];
+            gbs[seg].nchunk[k] = dw_chunks(dk, sk, nsp);
+            gbs[seg].chunk[k] = ((nsp + gbs[seg].nchunk[k] - 1) / gbs[seg].nchunk[k] + 31) / 32 * 32;
+        }
+    }
     {
-        const int64_t nsp = grad_nsp(b.ns), tot = (int64_t)d.N * nsp;
+        const int64_t tot = (int64_t)d.N * nsp;
         const int g2 = (int)((tot + 255) / 256 < 8192 ? (tot + 255) / 256 : 8192);
+        const dim3 grid(g2, nb > 0 ? nb : 1);
+        const int64_t pcfg = nb > 0 ? bi->pitch_cfg : 0;
         if (d.prec == VMC_BF16)
-            hipLaunchKernelGGL(build_extras<BF16>, dim3(g2), dim3(256), 0, st, d, b.ns, nsp, b.cfg, (uint16_t *)b.xT);
+            hipLaunchKernelGGL(build_extras<BF16>, grid, dim3(256), 0, st, d, b.ns, nsp, b.cfg, (uint16_t *)b.xT,
+                               gbs[0], pcfg);
         else
-            hipLaunchKernelGGL(build_extras<F32>, dim3(g2), dim3(256), 0, st, d, b.ns, nsp, b.cfg, (float *)b.xT);
+            hipLaunchKernelGGL(build_extras<F32>, grid, dim3(256), 0, st, d, b.ns, nsp, b.cfg, (float *)b.xT, gbs[0],
+                               pcfg);
     }
     const int64_t P = param_layout(d.dims, d.dh, d.glu, d.cplx).total;
-    hipLaunchKernelGGL(fill_f64, dim3((int)((P + 255) / 256 < 4096 ? (P + 255) / 256 : 4096)), dim3(256), 0, st,
-                       b.grad, P, 0.0);
+    const int64_t Pall = nb > 0 ? (int64_t)(nb - 1) * bi->pitch_p + P : P;
+    hipLaunchKernelGGL(fill_f64, dim3((int)((Pall + 255) / 256 < 4096 ? (Pall + 255) / 256 : 4096)), dim3(256), 0, st,
+                       b.grad, Pall, 0.0);
     for (int seg = 0; seg < 3; seg++) {
         if (seg == 1 && !d.glu) continue;
         SegDims sd = seg_dims(d, seg);
@@ -459,11 +527,16 @@ hipError_t launch_grad(const GradBufs &b, hipStream_t st) {
         a.units = d.N * a.nchunk;
         a.tiles_m = dw_tiles_m(sd);
         a.tiles = a.tiles_m * dw_tiles_n(sd);
-        if (d.prec == VMC_BF16) launch_dw_p<BF16>(a, sd, st);
-        else launch_dw_p<F32>(a, sd, st);
+        int units_max = a.units;
+        for (int k = 0; k < nb; k++) {
+            const int u = gbs[seg].N[k] * gbs[seg].nchunk[k];
+            units_max = u > units_max ? u : units_max;
+        }
+        if (d.prec == VMC_BF16) launch_dw_p<BF16>(a, sd, gbs[seg], units_max, st);
+        else launch_dw_p<F32>(a, sd, gbs[seg], units_max, st);
         const int rg = sd.MD * ((sd.K + 5 + 31) / 32);
-        hipLaunchKernelGGL(dw_reduce, dim3(rg), dim3(256), 0, st, d, seg, b.part, d.N * a.nchunk, sd.Mp, sd.Kp, sd.K,
-                           sd.MD, b.grad);
+        hipLaunchKernelGGL(dw_reduce, dim3(rg, nb > 0 ? nb : 1), dim3(256), 0, st, d, seg, b.part, d.N * a.nchunk,
+                           sd.Mp, sd.Kp, sd.K, sd.MD, b.grad, gbs[seg]);
     }
     return hipGetLastError();
 }

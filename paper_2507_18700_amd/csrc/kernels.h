@@ -163,4 +163,66 @@ __host__ __device__ inline void conn_sites(int kind, int c, int Lx, int Ly, int 
     }
 }
 
+// ------------------------------------------------------- batched problems
+// vmc_step_batched runs several independent chains (same cell shape, own
+// lengths, couplings and weights) through the same launches.  Problem k owns
+// a workspace region at k * pitch_ws laid out for the longest chain, so every
+// workspace pointer of problem k is the one of problem 0 shifted by that
+// pitch; its configurations, log-probabilities, parameters and gradient sit
+// in the caller's arrays at fixed pitches.  A kernel finds k from its tile
+// (the chain launch's global schedule) or from its grid index and rebases
+// its arguments.
+constexpr int kMaxBatch = 64;
+struct BatchInfo {
+    int n;                 // problems (0: not batched)
+    int tiles;             // row tiles per problem of the sampling / reverse-sweep launches
+    int64_t pitch_ws;      // bytes between workspace regions
+    int64_t pitch_cfg;     // bytes between configuration arrays (ns * longest chain)
+    int64_t pitch_p;       // entries between parameter / gradient vectors
+    int64_t ns;            // samples per problem
+    const int4 *sched;     // chain tiles of all problems, longest chains first:
+                           // {first tile, problem, first changed position, -}
+    int nsched;            // entries; sched[nsched].x = total tile count
+    int N[kMaxBatch];      // chain lengths
+};
+
+template <class T>
+__host__ __device__ inline T *shift_bytes(T *p, int64_t bytes) {
+    return p ? (T *)((char *)p + bytes) : p;
+}
+
+// Arguments of the forward engine for problem k of a batch.
+__device__ inline void rebase_fwd(FwdArgs &a, const BatchInfo &b, int k) {
+    const int64_t o = (int64_t)k * b.pitch_ws;
+    a.Bc = shift_bytes(a.Bc, o);
+    a.Bg = shift_bytes(a.Bg, o);
+    a.E = shift_bytes(a.E, o);
+    a.Hd = shift_bytes(a.Hd, o);
+    a.hc = shift_bytes(a.hc, o);
+    a.hcache = shift_bytes(a.hcache, o);
+    a.hcs = shift_bytes(a.hcs, o);
+    a.postab = shift_bytes(a.postab, o);
+    a.lpc = shift_bytes(a.lpc, o);
+    a.phc = shift_bytes(a.phc, o);
+    a.pre = shift_bytes(a.pre, o);
+    a.act = shift_bytes(a.act, o);
+    a.lgT = shift_bytes(a.lgT, o);
+    a.hT = shift_bytes(a.hT, o);
+    a.gT = shift_bytes(a.gT, o);
+    a.colbuf = shift_bytes(a.colbuf, o);
+    a.cnt = shift_bytes(a.cnt, o);
+    a.tile_start = shift_bytes(a.tile_start, o);
+    a.list_off = shift_bytes(a.list_off, o);
+    a.list = shift_bytes(a.list, o);
+    a.dsuf = shift_bytes(a.dsuf, o);
+    a.cfg_in = shift_bytes(a.cfg_in, (int64_t)k * b.pitch_cfg);
+    a.cfg_out = shift_bytes(a.cfg_out, (int64_t)k * b.pitch_cfg);
+    a.logp = shift_bytes(a.logp, (int64_t)k * b.ns * 4);
+    a.phase = shift_bytes(a.phase, (int64_t)k * b.ns * 4);
+    a.d.N = a.d.Lx = b.N[k];
+    a.seed += (uint64_t)k;
+    a.NC = a.ham_kind == 0 ? a.d.N : conn_count(a.ham_kind, a.d.N, 1);
+    a.nbond = a.ham_kind == 0 ? 0 : a.NC;
+}
+
 }  // namespace vmc

@@ -19,7 +19,8 @@ VMC_TFIM, VMC_HEISENBERG, VMC_LRTFIM, VMC_CLUSTER = 0, 1, 2, 3
 VMC_EINVAL, VMC_EUNSUPPORTED, VMC_ENOSPACE, VMC_EDEVICE, VMC_ENONFINITE = -1, -2, -3, -4, -5
 
 EXPORTS = ("vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "rnn_logpsi_grad", "local_energy",
-           "vmc_grad", "vmc_step", "vmc_step_noalloc", "vmc_noalloc_scratch_bytes", "vmc_adam", "vmc_check_finite",
+           "vmc_grad", "vmc_step", "vmc_step_batched", "vmc_batched_workspace_size", "vmc_step_noalloc",
+           "vmc_noalloc_scratch_bytes", "vmc_adam", "vmc_check_finite",
            "grow_hidden", "vmc_row_tile_options",
            "vmc_set_tuning", "vmc_get_tuning", "vmc_autotune_step", "vmc_chain_timing", "vmc_chain_time",
            "vmc_status_str")
@@ -99,6 +100,11 @@ def lib():
         L.vmc_grad.argtypes = [P(Model), vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
         L.vmc_step.restype = ctypes.c_int
         L.vmc_step.argtypes = [P(Model), vp, P(Ham), i64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.vmc_step_batched.restype = ctypes.c_int
+        L.vmc_step_batched.argtypes = [ctypes.c_int32, P(Model), P(ctypes.c_int32), P(Ham), vp, i64, u64, u64, vp, vp,
+                                       vp, vp, vp, vp, vp, vp, sz, vp]
+        L.vmc_batched_workspace_size.restype = ctypes.c_int
+        L.vmc_batched_workspace_size.argtypes = [ctypes.c_int32, P(Model), P(ctypes.c_int32), P(Ham), i64, P(sz)]
         L.vmc_step_noalloc.restype = ctypes.c_int
         L.vmc_step_noalloc.argtypes = [P(Model), vp, P(Ham), i64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.vmc_noalloc_scratch_bytes.restype = sz
@@ -350,6 +356,67 @@ def vmc_step(m, params, H, ns, seed=0, counter=0, uniforms=None, ws=None, out=No
                           _ptr(uniforms), _ptr(cfg), _ptr(lp), _ptr(ph), _ptr(e), _ptr(g), _ptr(st), _ptr(buf), nb,
                           _stream()))
     return cfg, lp, ph, e, g, st
+
+
+def _batch_args(m, chain_lens, hams):
+    n = len(chain_lens)
+    if n < 1 or len(hams) != n:
+        raise ValueError("one Hamiltonian per chain")
+    lens = (ctypes.c_int32 * n)(*[int(c) for c in chain_lens])
+    hs = (Ham * n)(*hams)
+    return n, lens, hs
+
+
+def batched_workspace_size(m, chain_lens, hams, ns):
+    n, lens, hs = _batch_args(m, chain_lens, hams)
+    out = ctypes.c_size_t(0)
+    _check(lib().vmc_batched_workspace_size(n, ctypes.byref(m), lens, hs, ns, ctypes.byref(out)))
+    return out.value
+
+
+def vmc_step_batched(m, chain_lens, hams, params, ns, seed=0, counter=0, ws=None, out=None, counter_dev=None):
+    """One VMC step of several 1D problems (own chain lengths, couplings and
+    weights, the cell shape of m) in shared launches.  params: [nprob, P]
+    float32.  Returns (configs [nprob, ns * Nmax] uint8, logp [nprob, ns],
+    phase [nprob, ns], eloc [nprob, ns, 2], grad [nprob, P], stats
+    [nprob, 4]); batch_configs() gives problem k's [ns, N_k] view.  Problem k
+    equals vmc_step on it alone with seed + k."""
+    n, lens, hs = _batch_args(m, chain_lens, hams)
+    P = param_count(m)
+    _dev(params, torch.float32, "params", (n, P))
+    nmax = max(int(c) for c in chain_lens)
+    dev = params.device
+    if out is None:
+        out = (torch.empty((n, ns * nmax), dtype=torch.uint8, device=dev),
+               torch.empty((n, ns), dtype=torch.float32, device=dev),
+               torch.empty((n, ns), dtype=torch.float32, device=dev),
+               torch.empty((n, ns, 2), dtype=torch.float64, device=dev),
+               torch.empty((n, P), dtype=torch.float64, device=dev),
+               torch.empty((n, 4), dtype=torch.float64, device=dev))
+    cfg, lp, ph, e, g, st = out
+    _dev(cfg, torch.uint8, "configs", (n, ns * nmax))
+    _dev(lp, torch.float32, "logp", (n, ns))
+    if ph is not None:
+        _dev(ph, torch.float32, "phase", (n, ns))
+    _dev(e, torch.float64, "eloc", (n, ns, 2))
+    _dev(g, torch.float64, "grad", (n, P))
+    _dev(st, torch.float64, "stats", (n, 4))
+    if counter_dev is not None:
+        _dev(counter_dev, torch.int64, "counter_dev", (1,))
+    need = batched_workspace_size(m, chain_lens, hams, ns)
+    if ws is None:
+        d = torch.cuda.current_device()
+        ws = _default_ws.setdefault(d, Workspace("cuda:%d" % d))
+    buf = ws.get(need)
+    _check(lib().vmc_step_batched(n, ctypes.byref(m), lens, hs, _ptr(params), ns, seed, counter, _ptr(counter_dev),
+                                  _ptr(cfg), _ptr(lp), _ptr(ph), _ptr(e), _ptr(g), _ptr(st), _ptr(buf), buf.numel(),
+                                  _stream()))
+    return out
+
+
+def batch_configs(configs, k, ns, n_k):
+    """Problem k's configurations [ns, n_k] inside the batched configs array."""
+    return configs[k, :ns * n_k].view(ns, n_k)
 
 
 def vmc_step_noalloc(m, params, H, ns, out, seed=0, counter=0, uniforms=None, counter_dev=None):

@@ -32,7 +32,8 @@ def lib():
 def test_exports_every_declared_symbol(lib):
     names = declared()
     assert set(names) == {"vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "rnn_logpsi_grad",
-                          "local_energy", "vmc_grad", "vmc_step", "vmc_step_noalloc", "vmc_noalloc_scratch_bytes",
+                          "local_energy", "vmc_grad", "vmc_step", "vmc_step_batched", "vmc_batched_workspace_size",
+                          "vmc_step_noalloc", "vmc_noalloc_scratch_bytes",
                           "vmc_adam", "vmc_check_finite", "grow_hidden",
                           "vmc_row_tile_options", "vmc_set_tuning", "vmc_get_tuning", "vmc_autotune_step",
                           "vmc_chain_timing", "vmc_chain_time", "vmc_status_str"}
