@@ -800,6 +800,52 @@ static void backward_one(const ora_model *m, const layout *L, const double *P, c
     trace_free(&t);
 }
 
+/* The same gradient with, per parameter, the sum over samples of the
+ * absolute per-sample contributions (absgrad), from which the cancellation
+ * factor kappa = |sum |t_s|| / |sum t_s| of a block follows.  The sum itself is
+ * formed per sample first, so its rounding may differ from
+ * ora_surrogate_grad's in the last bits. */
+void ora_surrogate_grad_abs(const ora_model *m, const double *P, int64_t ns, const uint8_t *cfg,
+                            const double *a, const double *b, double *grad, double *absgrad)
+{
+    layout L;
+    make_layout(m, &L);
+    int N = L.N;
+    long np = L.total;
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+#endif
+    double *part = calloc((size_t)2 * nt * np, sizeof(double));
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *gp = part + (size_t)2 * tid * np, *ap = gp + np;
+        double *ts = malloc(np * sizeof(double));
+#pragma omp for schedule(static)
+        for (int64_t s = 0; s < ns; s++) {
+            memset(ts, 0, np * sizeof(double));
+            backward_one(m, &L, P, cfg + s * N, a[s], b ? b[s] : 0.0, ts);
+            for (long k = 0; k < np; k++) {
+                gp[k] += ts[k];
+                ap[k] += fabs(ts[k]);
+            }
+        }
+        free(ts);
+    }
+    memset(grad, 0, np * sizeof(double));
+    memset(absgrad, 0, np * sizeof(double));
+    for (int t2 = 0; t2 < nt; t2++)
+        for (long k = 0; k < np; k++) {
+            grad[k] += part[(size_t)2 * t2 * np + k];
+            absgrad[k] += part[(size_t)(2 * t2 + 1) * np + k];
+        }
+    free(part);
+}
+
 /* Gradient of the surrogate L(theta) = sum_s [a_s logP(sigma_s) + b_s phi(sigma_s)]
  * with the configurations and the coefficients held fixed.  The per-thread
  * partial sums are added in thread order, so the result is reproducible for a
@@ -979,6 +1025,16 @@ void ora_adam(int64_t n, double *p, const double *g, double *m, double *v, int64
         double vh = v[i] / (1.0 - pow(b2, (double)t));
         p[i] -= lr * mh / (sqrt(vh) + eps);
     }
+}
+
+/* Threads of the OpenMP loops (the CPU baseline's one-core rate). */
+void ora_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 int32_t ora_num_threads(void)

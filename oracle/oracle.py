@@ -70,6 +70,8 @@ def lib():
         L.ora_round_bf16.restype = d
         L.ora_round_bf16.argtypes = [d]
         L.ora_adam.argtypes = [i64, P(d), P(d), P(d), P(d), i64, d, d, d, d]
+        L.ora_surrogate_grad_abs.argtypes = [P(Model), P(d), i64, P(u8), P(d), P(d), P(d), P(d)]
+        L.ora_set_threads.argtypes = [ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -182,6 +184,20 @@ def surrogate_grad(m, params, configs, a, b=None):
                              _p(configs, ctypes.c_uint8), _p(_f64(a)),
                              _p(None if b is None else _f64(b)), _p(g))
     return g
+
+
+def surrogate_grad_abs(m, params, configs, a, b=None):
+    """(gradient, per-entry sum over samples of |per-sample contribution|)."""
+    params, configs = _f64(params), _u8(configs)
+    g = np.zeros(param_count(m))
+    ga = np.zeros(param_count(m))
+    lib().ora_surrogate_grad_abs(ctypes.byref(m), _p(params), configs.shape[0], _p(configs, ctypes.c_uint8),
+                                 _p(_f64(a)), _p(None if b is None else _f64(b)), _p(g), _p(ga))
+    return g, ga
+
+
+def set_threads(n):
+    lib().ora_set_threads(int(n))
 
 
 def grad(m, params, configs, eloc, weights=None):

@@ -451,3 +451,19 @@ def test_bf16_mode_is_a_small_perturbation(ora):
     assert abs(np.exp(lpb).sum() - 1.0) < 1e-12
     d = np.abs(lpb - lp)
     assert d.max() > 0 and (np.exp(lp) * d).sum() < 0.02
+
+
+def test_surrogate_grad_abs(ora):
+    """The per-sample path of the gradient sums to the same gradient, and its
+    sum of |contributions| bounds |gradient| entrywise, with equality for one
+    sample."""
+    spec, m, p = make(ora, VARIANTS_2D[1], seed=5)
+    cfg = synth.configs(9, spec.N, 6)
+    rng = np.random.default_rng(7)
+    a, b = rng.standard_normal(9), rng.standard_normal(9)
+    g = ora.surrogate_grad(m, p, cfg, a, b)
+    g2, ga = ora.surrogate_grad_abs(m, p, cfg, a, b)
+    assert np.max(np.abs(g2 - g)) <= 1e-12 * np.max(np.abs(g))
+    assert np.all(ga >= np.abs(g2) - 1e-15)
+    g1, ga1 = ora.surrogate_grad_abs(m, p, cfg[:1], a[:1], b[:1])
+    assert np.array_equal(ga1, np.abs(g1))
