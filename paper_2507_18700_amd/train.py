@@ -254,48 +254,64 @@ class Trainer:
 def _main():
     import argparse
     import json
-    ap = argparse.ArgumentParser(description="VMC training of a 1D RNN wave function (Static or Adaptive)")
-    ap.add_argument("--ham", default="tfim", choices=["tfim", "lrtfim", "cluster"])
-    ap.add_argument("--N", type=int, default=20)
+    ap = argparse.ArgumentParser(description="VMC training of an RNN wave function (Static, Adaptive or "
+                                             "Adaptive with early stopping), Table III settings")
+    ap.add_argument("--ham", default="tfim", choices=["tfim", "heisenberg", "lrtfim", "cluster"])
+    ap.add_argument("--N", type=int, default=20, help="chain length, or Lx of a 2D lattice")
+    ap.add_argument("--Ly", type=int, default=1, help="> 1: 2D zig-zag RNN with GLU on an N x Ly lattice")
     ap.add_argument("--mode", default="static", choices=["static", "adaptive", "early"])
     ap.add_argument("--d-final", type=int, default=256)
     ap.add_argument("--d-start", type=int, default=2)
     ap.add_argument("--steps", type=int, default=50000)
     ap.add_argument("--ns", type=int, default=100)
-    ap.add_argument("--lr", type=float, default=5e-4)
-    ap.add_argument("--lr-first", type=float, default=None, help="first-half learning rate (two-stage schedule)")
+    ap.add_argument("--lr", type=float, default=None,
+                    help="learning rate (default 5e-4; early stopping: the rate from d_h = 64 on, default 1e-4)")
+    ap.add_argument("--lr-first", type=float, default=None,
+                    help="static/adaptive: rate of the first half (two-value schedule); early: rate below d_h = 64")
+    ap.add_argument("--decay-start", type=int, default=0, help="step from which the rate decays")
+    ap.add_argument("--decay-tau", type=float, default=0.0, help="lr / (1 + (k - start) / tau); 0: no decay")
     ap.add_argument("--h", type=float, default=1.0)
+    ap.add_argument("--J", type=float, default=1.0)
     ap.add_argument("--alpha", type=float, default=0.1)
+    ap.add_argument("--marshall", action="store_true", help="Heisenberg with the Marshall sign rule")
     ap.add_argument("--complex", action="store_true")
+    ap.add_argument("--bf16", action="store_true", help="BF16 MFMA operands")
     ap.add_argument("--eval-samples", type=int, default=10 ** 6)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--quiet", action="store_true")
     a = ap.parse_args()
-    kinds = {"tfim": V.VMC_TFIM, "lrtfim": V.VMC_LRTFIM, "cluster": V.VMC_CLUSTER}
-    H = V.ham(kinds[a.ham], J=1.0, h=a.h, alpha=a.alpha)
+    kinds = {"tfim": V.VMC_TFIM, "heisenberg": V.VMC_HEISENBERG, "lrtfim": V.VMC_LRTFIM, "cluster": V.VMC_CLUSTER}
+    H = V.ham(kinds[a.ham], J=a.J, h=a.h, marshall=a.marshall, alpha=a.alpha)
+    decay = dict(t_decay=a.decay_start, tau=a.decay_tau)
     if a.mode == "static":
         stages = static_stages(a.d_final, a.steps)
     elif a.mode == "adaptive":
         n_st = int(round(math.log2(a.d_final / a.d_start))) + 1
         stages = adaptive_stages(a.d_start, a.d_final, a.steps // n_st)
     else:
-        # early stopping (Table III): 0.01 below d_h = 64, then the final rate
-        hi = V.adam_cfg(lr0=a.lr_first if a.lr_first is not None else 1e-2)
-        stages = [Stage(d, 0, hi if d < 64 else V.adam_cfg(lr0=a.lr))
+        # early stopping (Table III): 0.01 below d_h = 64, 1e-4 from d_h = 64 on
+        hi = V.adam_cfg(lr0=a.lr_first if a.lr_first is not None else 1e-2, **decay)
+        lo = V.adam_cfg(lr0=a.lr if a.lr is not None else 1e-4, **decay)
+        stages = [Stage(d, 0, hi if d < 64 else lo)
                   for d in (2 ** k for k in range(int(math.log2(a.d_start)), int(math.log2(a.d_final)) + 1))]
+    lr = a.lr if a.lr is not None else 5e-4
     if a.lr_first is not None and a.mode != "early":
-        adam = V.adam_cfg(lr0=a.lr_first, lr1=a.lr, t_switch=a.steps // 2)
+        adam = V.adam_cfg(lr0=a.lr_first, lr1=lr, t_switch=a.steps // 2, **decay)
     else:
-        adam = V.adam_cfg(lr0=a.lr)
-    tr = Trainer(dict(dims=1, Lx=a.N, is_complex=a.complex), H, a.ns, stages, adam, seed=a.seed)
+        adam = V.adam_cfg(lr0=lr, **decay)
+    two_d = a.Ly > 1
+    model = dict(dims=2 if two_d else 1, Lx=a.N, Ly=a.Ly, is_complex=a.complex, glu=two_d,
+                 precision=V.VMC_BF16 if a.bf16 else V.VMC_FP32)
+    tr = Trainer(model, H, a.ns, stages, adam, seed=a.seed)
     res = tr.run(log=None if a.quiet else (lambda s: print(s, flush=True)))
-    out = dict(ham=a.ham, N=a.N, mode=a.mode, stages=[s.d_h for s in stages], stage_steps=res.stage_steps,
+    n_sites = a.N * a.Ly
+    out = dict(ham=a.ham, N=a.N, Ly=a.Ly, mode=a.mode, stages=[s.d_h for s in stages], stage_steps=res.stage_steps,
                ns=a.ns, train_wall_s=round(res.wall_s, 2), train_samples_per_s=round(res.samples / res.wall_s, 1),
                ms_per_step=round(1e3 * res.wall_s / max(1, res.energy.size), 4),
                last_energy_mean_1000=float(res.energy[-1000:].mean()))
     if a.eval_samples > 0:
         E, dE, var, dvar = tr.evaluate(a.eval_samples)
-        out.update(energy=E, energy_err=dE, var_per_spin=var / a.N, var_per_spin_err=dvar / a.N,
+        out.update(energy=E, energy_err=dE, var_per_spin=var / n_sites, var_per_spin_err=dvar / n_sites,
                    eval_samples=a.eval_samples)
     print(json.dumps(out), flush=True)
 
