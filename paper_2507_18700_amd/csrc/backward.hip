@@ -320,7 +320,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a0, BatchInfo bi) {
 
         // register-resident weights leave room to load the gate values before the
         // GLU input-gradient MFMAs (their latency then overlaps that phase)
-        RawF fcr[NA][RB][UB];
+        RawF fcr[NA][RB][UB];  // (streamed weights: loaded after the GLU input gradient)
         if (REGW) {
 #pragma unroll
             for (int f = 0; f < NA; f++)
@@ -336,34 +336,65 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a0, BatchInfo bi) {
 #pragma unroll
             for (int ub = 0; ub < UB; ub++) accg[rb][ub] = f32x4_t{0.f, 0.f, 0.f, 0.f};
         if (glu) {
+            if constexpr (REGW) {
 #pragma unroll
-            for (int ks = 0; ks < NGK; ks++) {
-                uint4 af[RB];
+                for (int ks = 0; ks < NGK; ks++) {
+                    uint4 af[RB];
 #pragma unroll
-                for (int rb = 0; rb < RB; rb++)
-                    af[rb] = *(const uint4 *)&sD[(wr * C::RW + rb * 16 + l16) * D_LD + ks * KS + VEC * lq];
+                    for (int rb = 0; rb < RB; rb++)
+                        af[rb] = *(const uint4 *)&sD[(wr * C::RW + rb * 16 + l16) * D_LD + ks * KS + VEC * lq];
 #pragma unroll
-                for (int ub = 0; ub < UB; ub++) {
-                    uint4 bf;
-                    const int k = wu * C::UW + ub * 16 + l16;
-                    if (REGW) bf = *(const uint4 *)&sBg[k * G_LD + ks * KS + VEC * lq];
-                    else bf = *(const uint4 *)&BgT[(int64_t)k * 2 * DH + ks * KS + VEC * lq];
+                    for (int ub = 0; ub < UB; ub++) {
+                        const int k = wu * C::UW + ub * 16 + l16;
+                        const uint4 bf = *(const uint4 *)&sBg[k * G_LD + ks * KS + VEC * lq];
 #pragma unroll
-                    for (int rb = 0; rb < RB; rb++) P::mma(accg[rb][ub], af[rb], bf);
+                        for (int rb = 0; rb < RB; rb++) P::mma(accg[rb][ub], af[rb], bf);
+                    }
+                }
+            } else {
+                // streamed weights: the next k-step's fragments in flight (a
+                // bounded prefetch; a full unroll hoists every load and spills)
+                uint4 bw0[UB], bw1[UB];
+                auto wload = [&](int ks, uint4 *bw) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int ub = 0; ub < UB; ub++) {
+                        const int k = wu * C::UW + ub * 16 + l16;
+                        bw[ub] = *(const uint4 *)&BgT[(int64_t)k * 2 * DH + ks * KS + VEC * lq];
+                    }
+                };
+                auto kstep = [&](int ks, const uint4 *bw) __attribute__((always_inline)) {
+                    uint4 af[RB];
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++)
+                        af[rb] = *(const uint4 *)&sD[(wr * C::RW + rb * 16 + l16) * D_LD + ks * KS + VEC * lq];
+#pragma unroll
+                    for (int ub = 0; ub < UB; ub++)
+#pragma unroll
+                        for (int rb = 0; rb < RB; rb++) P::mma(accg[rb][ub], af[rb], bw[ub]);
+                };
+                wload(0, bw0);
+#pragma unroll 1
+                for (int ks = 0; ks < NGK; ks += 2) {
+                    if (ks + 1 < NGK) wload(ks + 1, bw1);
+                    kstep(ks, bw0);
+                    if (ks + 1 < NGK) {
+                        if (ks + 2 < NGK) wload(ks + 2, bw0);
+                        kstep(ks + 1, bw1);
+                    }
                 }
             }
             __syncthreads();  // GLU deltas read before the cell deltas overwrite the tile
         }
 
-        // gate values of this step
-        float4 fc[NA][RB][UB];
+        // gate values of this step, as stored (widened at use: half the registers)
+        if (!REGW) {
 #pragma unroll
-        for (int f = 0; f < NA; f++)
+            for (int f = 0; f < NA; f++)
 #pragma unroll
-            for (int rb = 0; rb < RB; rb++)
+                for (int rb = 0; rb < RB; rb++)
 #pragma unroll
-                for (int ub = 0; ub < UB; ub++)
-                    fc[f][rb][ub] = widen(REGW ? fcr[f][rb][ub] : feat(q, f, wu * C::UW + ub * 16 + l16, rb));
+                    for (int ub = 0; ub < UB; ub++) fcr[f][rb][ub] = feat(q, f, wu * C::UW + ub * 16 + l16, rb);
+        }
         float4 fhp[DIMS == 1 ? RB : 1][DIMS == 1 ? UB : 1];  // 1D: h_{n-1} (FP32)
         if (DIMS == 1) {
 #pragma unroll
@@ -391,12 +422,12 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a0, BatchInfo bi) {
             for (int ub = 0; ub < UB; ub++) {
                 const int u = wu * C::UW + ub * 16 + l16;
                 float gd[4][4];
-                const float4 f0 = fc[0][rb][ub], f1 = fc[1][rb][ub], f2 = fc[2][rb][ub];
+                const float4 f0 = widen(fcr[0][rb][ub]), f1 = widen(fcr[1][rb][ub]), f2 = widen(fcr[2][rb][ub]);
                 const float v0[4] = {f0.x, f0.y, f0.z, f0.w}, v1[4] = {f1.x, f1.y, f1.z, f1.w};
                 const float v2[4] = {f2.x, f2.y, f2.z, f2.w};
                 float v3[4] = {0.f, 0.f, 0.f, 0.f}, hp[4] = {0.f, 0.f, 0.f, 0.f};
                 if (DIMS == 1) {
-                    const float4 f3 = fc[NA - 1][rb][ub];
+                    const float4 f3 = widen(fcr[NA - 1][rb][ub]);
                     v3[0] = f3.x; v3[1] = f3.y; v3[2] = f3.z; v3[3] = f3.w;
                     const float4 h4 = fhp[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)];
                     hp[0] = h4.x; hp[1] = h4.y; hp[2] = h4.z; hp[3] = h4.w;
@@ -450,23 +481,47 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a0, BatchInfo bi) {
         for (int rb = 0; rb < RB; rb++)
 #pragma unroll
             for (int c = 0; c < NOB; c++) accx[rb][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        if constexpr (REGW) {
 #pragma unroll
-        for (int ks = 0; ks < NCK; ks++) {
-            uint4 af[RB];
+            for (int ks = 0; ks < NCK; ks++) {
+                uint4 af[RB];
 #pragma unroll
-            for (int rb = 0; rb < RB; rb++)
-                af[rb] = *(const uint4 *)&sD[(wr * C::RW + rb * 16 + l16) * D_LD + ks * KS + VEC * lq];
+                for (int rb = 0; rb < RB; rb++)
+                    af[rb] = *(const uint4 *)&sD[(wr * C::RW + rb * 16 + l16) * D_LD + ks * KS + VEC * lq];
 #pragma unroll
-            for (int c = 0; c < NOB; c++) {
-                uint4 bf;
-                if (REGW) {
-                    bf = wc[REGW ? ks : 0][REGW ? c : 0];
-                } else {
+                for (int c = 0; c < NOB; c++)
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++) P::mma(accx[rb][c], af[rb], wc[REGW ? ks : 0][REGW ? c : 0]);
+            }
+        } else {
+            // streamed weights: the next k-step's fragments in flight
+            uint4 bw0[NOB], bw1[NOB];
+            auto wload = [&](int ks, uint4 *bw) __attribute__((always_inline)) {
+#pragma unroll
+                for (int c = 0; c < NOB; c++) {
                     const int k = (c / UB) * DH + wu * C::UW + (c % UB) * 16 + l16;
-                    bf = *(const uint4 *)&BcT[(int64_t)k * NCP + ks * KS + VEC * lq];
+                    bw[c] = *(const uint4 *)&BcT[(int64_t)k * NCP + ks * KS + VEC * lq];
                 }
+            };
+            auto kstep = [&](int ks, const uint4 *bw) __attribute__((always_inline)) {
+                uint4 af[RB];
 #pragma unroll
-                for (int rb = 0; rb < RB; rb++) P::mma(accx[rb][c], af[rb], bf);
+                for (int rb = 0; rb < RB; rb++)
+                    af[rb] = *(const uint4 *)&sD[(wr * C::RW + rb * 16 + l16) * D_LD + ks * KS + VEC * lq];
+#pragma unroll
+                for (int c = 0; c < NOB; c++)
+#pragma unroll
+                    for (int rb = 0; rb < RB; rb++) P::mma(accx[rb][c], af[rb], bw[c]);
+            };
+            wload(0, bw0);
+#pragma unroll 1
+            for (int ks = 0; ks < NCK; ks += 2) {
+                if (ks + 1 < NCK) wload(ks + 1, bw1);
+                kstep(ks, bw0);
+                if (ks + 1 < NCK) {
+                    if (ks + 2 < NCK) wload(ks + 2, bw0);
+                    kstep(ks + 1, bw1);
+                }
             }
         }
 #pragma unroll

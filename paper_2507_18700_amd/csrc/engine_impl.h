@@ -40,10 +40,12 @@
 namespace vmc {
 
 // Tile shape by tile class TC.  TC = 1: the suffix-chain launch (persistent).
-// TC = 0: one tile per work-group over the samples (sampling, log psi), made
-// shorter at bfloat16 d_h = 128 (48 rows) so that 10^4 samples occupy more
-// compute units.  TC = 2: the alternative row tile that the tuning table can
-// select (64 rows there, half the chain tile elsewhere); where it does not
+// TC = 0: one tile per work-group over the samples (sampling, log psi); at
+// bfloat16 d_h = 128 the 1D tile is made shorter (48 rows) so that 10^4
+// samples occupy more compute units, while the 2D tile keeps 64 rows (its
+// vertical-input prefetch makes the taller tile the faster one).  TC = 2: the
+// alternative row tile that the tuning table can select (the other of 48 and
+// 64 at bfloat16 d_h = 128, half the chain tile elsewhere); where it does not
 // exist (HAS_ALT false) TC = 2 has the TC = 0 shape and is never launched.
 // Every row of a tile is computed independently of the others, so the tile
 // choice does not change any result bit.
@@ -58,8 +60,8 @@ struct Eng {
     static constexpr int MT_CHAIN =
         (P::VEC == 4 && DH >= 128) ? 32 : DH >= 256 ? (P::VEC == 8 && NW == 8 ? 48 : 32) : 64;
     static constexpr bool BIG = P::VEC == 8 && DH == 128 && NW == 8;
-    static constexpr int MT_ROW = BIG ? 48 : MT_CHAIN;
-    static constexpr int MT_ALT = BIG ? 64 : MT_CHAIN / 2;
+    static constexpr int MT_ROW = BIG ? (DIMS == 2 ? 64 : 48) : MT_CHAIN;
+    static constexpr int MT_ALT = BIG ? (DIMS == 2 ? 48 : 64) : MT_CHAIN / 2;
     static constexpr bool HAS_ALT = MT_ALT != MT_ROW && MT_ALT % (16 * WR) == 0;
     static constexpr int MT = TC == 1 ? MT_CHAIN : (TC == 2 && HAS_ALT) ? MT_ALT : MT_ROW;
     static constexpr int RW = MT / WR;
@@ -484,38 +486,44 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
         // -------------------------------------------------- phase pieces
         // vertical input rows of a position (2D, not the row start): from the
         // prefix cache (positions <= p) or from the column buffer
-        uint4 pfv[PF];
+        // (the prefetched chunks are a value passed from vt_issue to vt_store, so
+        // that they live in registers for one phase, not in a private array)
+        struct Pfv {
+            uint4 v[PF];
+        };
         auto vt_needed = [&](int qn, const PosInfo &pi) __attribute__((always_inline)) {
             return DIMS == 2 && pi.site_vt >= 0 && pi.pos_vt < qn - 1;
         };
         // (chunk e of a tile is row e / (DH / VEC), columns (e % (DH / VEC)) * VEC:
         // offset e * VEC in a row-major [MT][DH] block, so the column buffer is
         // addressed as a uniform base plus a 32-bit per-lane offset)
-        auto vt_issue = [&](const PosInfo &pi) __attribute__((always_inline)) {
+        auto vt_issue = [&](const PosInfo &pi) -> Pfv __attribute__((always_inline)) {
             const bool cache = CHAIN && pi.pos_vt <= p;
             const T *cb = colbuf + (int64_t)pi.icol * (MT * DH);
+            Pfv f;
 #pragma unroll
             for (int i = 0; i < PF; i++) {
                 const int e = tid + i * NT;
+                f.v[i] = make_uint4(0, 0, 0, 0);
                 if (e < NCH) {
                     if (cache) {
                         const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
                         const int s = sRow[r];
-                        pfv[i] = s >= 0 ? *(const uint4 *)&hcs[((int64_t)pi.pos_vt * ns_c + s) * DH + c]
-                                        : make_uint4(0, 0, 0, 0);
+                        if (s >= 0) f.v[i] = *(const uint4 *)&hcs[((int64_t)pi.pos_vt * ns_c + s) * DH + c];
                     } else {
-                        pfv[i] = *(const uint4 *)(cb + (uint32_t)(e * VEC));
+                        f.v[i] = *(const uint4 *)(cb + (uint32_t)(e * VEC));
                     }
                 }
             }
+            return f;
         };
-        auto vt_store = [&](int buf) __attribute__((always_inline)) {
+        auto vt_store = [&](int buf, const Pfv &f) __attribute__((always_inline)) {
 #pragma unroll
             for (int i = 0; i < PF; i++) {
                 const int e = tid + i * NT;
                 if (e < NCH) {
                     const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
-                    *(uint4 *)&sV[DIMS == 2 ? buf : 0][r * H_LD + c] = pfv[i];
+                    *(uint4 *)&sV[DIMS == 2 ? buf : 0][r * H_LD + c] = f.v[i];
                 }
             }
         };
@@ -887,17 +895,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
         if (TF) {
             const int q0 = p + 1;
             const PosInfo P0 = pos(q0);
-            if (vt_needed(q0, P0)) {
-                vt_issue(P0);
-                vt_store(q0 & 1);
-            }
+            if (vt_needed(q0, P0)) vt_store(q0 & 1, vt_issue(P0));
             indicator(P0, q0 & 1, 0);
             if (q0 + 1 < N) {
                 const PosInfo P1 = pos(q0 + 1);
-                if (vt_needed(q0 + 1, P1)) {
-                    vt_issue(P1);
-                    vt_store((q0 + 1) & 1);
-                }
+                if (vt_needed(q0 + 1, P1)) vt_store((q0 + 1) & 1, vt_issue(P1));
                 indicator(P1, (q0 + 1) & 1, NW / 2);
             }
             __syncthreads();
@@ -910,7 +912,8 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
                 const PosInfo Pn = has_next ? pos(q + 1) : Pc;
                 const PosInfo P2 = has_2 ? pos(q + 2) : Pc;
                 const bool vt2 = has_2 && vt_needed(q + 2, P2);
-                if (vt2) vt_issue(P2);
+                Pfv f2;
+                if (vt2) f2 = vt_issue(P2);
                 if (Pc.colw) col_copy(q, Pc);
                 // indicator of q+2 (its own buffer) and finalisation of q-1
                 // (head sums complete since the last barrier), each by one wave
@@ -919,7 +922,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
                     if (q > q0) finalize(q - 1, Pp, (q - 1) % NW);
                 };
                 phase(glu, q, has_next, q + 1, Pn, mid);
-                if (vt2) vt_store(q & 1);
+                if (vt2) vt_store(q & 1, f2);
                 __syncthreads();
                 Pp = Pc;
                 Pc = Pn;
@@ -934,10 +937,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
                 const bool has_next = q + 1 < N;
                 const PosInfo Pn = has_next ? pos(q + 1) : Pc;
                 const bool vtn = has_next && vt_needed(q + 1, Pn);
-                if (vtn) vt_issue(Pn);
+                Pfv fn;
+                if (vtn) fn = vt_issue(Pn);
                 auto nop = []() __attribute__((always_inline)) {};
                 phase(false, q, true, q, Pc, nop);
-                if (vtn) vt_store((q + 1) & 1);
+                if (vtn) vt_store((q + 1) & 1, fn);
                 __syncthreads();
                 if (Pc.colw) col_copy(q, Pc);
                 if (glu) phase(true, q, false, q, Pc, nop);

@@ -18,6 +18,12 @@ namespace vmc {
 
 constexpr int DW_TILE = 128;            // padding granule of the weight-gradient partials
 constexpr int DW_NF = 9, DW_COLS = 144;  // input-column fragments / columns per contraction tile
+// MFMA k-steps per pipeline step of the contraction: two for the 3-fragment
+// tiles (one work-group per compute unit by registers, so the step size sets
+// the bytes in flight); one for the smaller tiles, which keep two or more
+// work-groups per compute unit that way
+template <int MF>
+constexpr int dw_sub() { return MF == 3 ? 2 : 1; }
 
 // ------------------------------------------------------------- statistics
 
@@ -153,10 +159,14 @@ __global__ void build_extras(Dims d, int64_t ns, int64_t nsp, const uint8_t *cfg
 
 // dW[m][k] at one position q over one chunk of samples: the sum over samples
 // of A[q][m][s] X[q][k][s] on MFMA.  A work-group of 8 waves covers 128*MF
-// delta rows (MF 16-row fragments per wave, read straight from memory, the
-// next k-step's in flight) against one tile of DW_COLS input columns that the
-// whole work-group stages in LDS (double-buffered), so each input row is read
-// from memory once per row tile instead of once per wave.
+// delta rows (MF 16-row fragments per wave, read straight from memory)
+// against one tile of DW_COLS input columns that the whole work-group stages
+// in LDS (double-buffered), so each input row is read from memory once per
+// row tile instead of once per wave.  A pipeline step spans dw_sub<MF>()
+// MFMA k-steps, and the next step's loads are in flight during the current
+// step's MFMAs: the contraction is bound by memory latency, so the bytes in
+// flight per compute unit set its rate.  Each accumulator takes its k-steps
+// in sample order whatever the step size.
 template <class P, int MF>
 __global__ __launch_bounds__(512) void dw_mfma(DwArgs a, DwBatch gb) {
     typedef typename P::store_t T;
@@ -173,9 +183,10 @@ __global__ __launch_bounds__(512) void dw_mfma(DwArgs a, DwBatch gb) {
         a.chunk = gb.chunk[k];
         a.units = a.d.N * a.nchunk;
     }
-    constexpr int VEC = P::VEC, KS = P::KSTEP;
-    constexpr int LDB = KS + 16 / (int)sizeof(T);  // padded row of the staged input tile
-    constexpr int CPR = KS / VEC;                  // 16-byte chunks per staged row
+    constexpr int DW_SUB = dw_sub<MF>();
+    constexpr int VEC = P::VEC, KS = P::KSTEP, STEP = DW_SUB * KS;
+    constexpr int LDB = STEP + 16 / (int)sizeof(T);  // padded row of the staged input tile
+    constexpr int CPR = STEP / VEC;                  // 16-byte chunks per staged row
     constexpr int NCH = DW_COLS * CPR, CPT = (NCH + 511) / 512;
     __shared__ __align__(16) T sB[2][DW_COLS * LDB];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, lq = lane >> 4;
@@ -199,13 +210,15 @@ __global__ __launch_bounds__(512) void dw_mfma(DwArgs a, DwBatch gb) {
         ap[i] = A + (int64_t)(m < a.MD ? m : 0) * nsp + VEC * lq;
     }
     // staging chunks of this thread: row j of the tile, 16-byte part c
+    // (samples VEC*c .. VEC*c + VEC - 1 of the step)
     const T *bsrc[CPT];
-    int bdst[CPT];
+    int bdst[CPT], boff[CPT];
 #pragma unroll
     for (int i = 0; i < CPT; i++) {
         const int ch = tid + 512 * i, j = ch / CPR, c = ch - j * CPR;
         bsrc[i] = nullptr;
         bdst[i] = -1;
+        boff[i] = VEC * c;
         if (ch < NCH) {
             bool extra;
             const int64_t off = dw_source(a, q, k0 + j, extra);
@@ -229,49 +242,57 @@ __global__ __launch_bounds__(512) void dw_mfma(DwArgs a, DwBatch gb) {
     for (int i = 0; i < MF; i++)
 #pragma unroll
         for (int f = 0; f < DW_NF; f++) acc[i][f] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    // (send and every chunk start are multiples of 32 samples, so a 16-byte
+    // part or a k-step lies wholly before or wholly after send; parts past
+    // send are zeros)
     uint4 stg[CPT];
     auto gload_b = [&](int64_t s0) {
 #pragma unroll
         for (int i = 0; i < CPT; i++)
-            stg[i] = (bsrc[i] && s0 < send) ? *(const uint4 *)(bsrc[i] + s0) : make_uint4(0, 0, 0, 0);
+            stg[i] = (bsrc[i] && s0 + boff[i] < send) ? *(const uint4 *)(bsrc[i] + s0) : make_uint4(0, 0, 0, 0);
     };
     auto sstore_b = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < CPT; i++)
             if (bdst[i] >= 0) *(uint4 *)&sB[buf][bdst[i]] = stg[i];
     };
-    auto load_a = [&](int64_t s0, uint4 *fa) {
+    auto load_a = [&](int64_t s0, uint4 (*fa)[MF]) {
 #pragma unroll
-        for (int i = 0; i < MF; i++)
-            fa[i] = (mon[i] && s0 < send) ? *(const uint4 *)(ap[i] + s0) : make_uint4(0, 0, 0, 0);
-    };
-    // one k-step on buffer buf with fragments fa; the next k-step's loads
-    // (into fn and the other buffer) are issued before the MFMAs
-    auto body = [&](int64_t s0, int buf, const uint4 *fa, uint4 *fn) {
-        const bool more = s0 + KS < send;  // uniform over the work-group
-        if (more) {
-            gload_b(s0 + KS);
-            load_a(s0 + KS, fn);
-        }
-#pragma unroll
-        for (int f = 0; f < DW_NF; f++) {
-            if (!kon[f]) continue;
-            const uint4 bf = *(const uint4 *)&sB[buf][(16 * f + l16) * LDB + VEC * lq];
+        for (int j = 0; j < DW_SUB; j++)
 #pragma unroll
             for (int i = 0; i < MF; i++)
-                if (mon[i]) P::mma(acc[i][f], fa[i], bf);
+                fa[j][i] = (mon[i] && s0 + j * KS < send) ? *(const uint4 *)(ap[i] + s0 + j * KS)
+                                                          : make_uint4(0, 0, 0, 0);
+    };
+    // one step on buffer buf with fragments fa; the next step's loads (into
+    // fn and the other buffer) are issued before the MFMAs
+    auto body = [&](int64_t s0, int buf, uint4 (*fa)[MF], uint4 (*fn)[MF]) {
+        const bool more = s0 + STEP < send;  // uniform over the work-group
+        if (more) {
+            gload_b(s0 + STEP);
+            load_a(s0 + STEP, fn);
         }
+#pragma unroll
+        for (int j = 0; j < DW_SUB; j++)
+#pragma unroll
+            for (int f = 0; f < DW_NF; f++) {
+                if (!kon[f]) continue;
+                const uint4 bf = *(const uint4 *)&sB[buf][(16 * f + l16) * LDB + j * KS + VEC * lq];
+#pragma unroll
+                for (int i = 0; i < MF; i++)
+                    if (mon[i]) P::mma(acc[i][f], fa[j][i], bf);
+            }
         if (more) sstore_b(buf ^ 1);
         __syncthreads();
     };
-    uint4 fa0[MF], fa1[MF];
+    uint4 fa0[DW_SUB][MF], fa1[DW_SUB][MF];
     gload_b(sbeg);
     sstore_b(0);
     load_a(sbeg, fa0);
     __syncthreads();
-    for (int64_t s0 = sbeg; s0 < send; s0 += 2 * KS) {
+    for (int64_t s0 = sbeg; s0 < send; s0 += 2 * STEP) {
         body(s0, 0, fa0, fa1);
-        if (s0 + KS < send) body(s0 + KS, 1, fa1, fa0);
+        if (s0 + STEP < send) body(s0 + STEP, 1, fa1, fa0);
     }
     float *out = a.part + (int64_t)u * a.Mp * a.Kp;
 #pragma unroll

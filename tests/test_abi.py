@@ -171,13 +171,15 @@ def test_tuning_table(lib):
     checks (host-only calls); the workspace size does not depend on it."""
     m = lib.model(dims=2, Lx=10, Ly=10, d_h=128, glu=True, precision=lib.VMC_BF16)
     H = lib.ham(lib.VMC_TFIM, 1.0, 3.0)
-    assert lib.row_tile_options(m) == [48, 64]
+    assert lib.row_tile_options(m) == [64, 48]
     builtin = lib.get_tuning(m)  # the chain default comes from the occupancy query (2 without a GPU)
-    assert builtin["row_tile"] == 48 and 1 <= builtin["chain_wgs_per_cu"] <= 4
+    assert builtin["row_tile"] == 64 and 1 <= builtin["chain_wgs_per_cu"] <= 4
+    # the 1D model of the same width starts from the shorter tile
+    assert lib.row_tile_options(lib.model(dims=1, Lx=20, d_h=128, precision=lib.VMC_BF16)) == [48, 64]
     need = lib.workspace_size(m, H, 10000)
-    lib.set_tuning(m, row_tile=64, chain_wgs_per_cu=4)
+    lib.set_tuning(m, row_tile=48, chain_wgs_per_cu=4)
     try:
-        assert lib.get_tuning(m) == {"row_tile": 64, "chain_wgs_per_cu": 4}
+        assert lib.get_tuning(m) == {"row_tile": 48, "chain_wgs_per_cu": 4}
         assert lib.workspace_size(m, H, 10000) == need
         # another shape is untouched
         m2 = lib.model(dims=2, Lx=10, Ly=10, d_h=128, glu=True, precision=lib.VMC_FP32)
@@ -188,7 +190,7 @@ def test_tuning_table(lib):
                 lib.set_tuning(m, **bad)
             assert e.value.status == -1
         # a rejected call leaves the table as it was
-        assert lib.get_tuning(m) == {"row_tile": 64, "chain_wgs_per_cu": 4}
+        assert lib.get_tuning(m) == {"row_tile": 48, "chain_wgs_per_cu": 4}
     finally:
         lib.reset_tuning(m)
     assert lib.get_tuning(m) == builtin
@@ -199,11 +201,11 @@ def test_tuning_table(lib):
     import tempfile
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "tuning.json")
-        lib.set_tuning(m, row_tile=64, chain_wgs_per_cu=1)
+        lib.set_tuning(m, row_tile=48, chain_wgs_per_cu=1)
         lib.save_tuning(path, [m, m3])
         lib.reset_tuning(m)
         assert lib.load_tuning(path, [m, m3]) == 2
-        assert lib.get_tuning(m) == {"row_tile": 64, "chain_wgs_per_cu": 1}
+        assert lib.get_tuning(m) == {"row_tile": 48, "chain_wgs_per_cu": 1}
         lib.reset_tuning(m)
         lib.reset_tuning(m3)
 

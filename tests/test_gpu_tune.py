@@ -12,10 +12,10 @@ from tests.gpu_util import lib_and_oracle, torch_gpu
 pytestmark = pytest.mark.gpu
 
 CASES = [
-    (2, 4, 4, 128, False, True, "tfim", True),   # bf16 d_h = 128: row tiles 48 / 64
+    (2, 4, 4, 128, False, True, "tfim", True),   # bf16 d_h = 128: row tiles 64 / 48
     (2, 5, 3, 20, True, True, "heis", False),    # fp32 d_h = 32 (padded): 64 / 32
     (1, 20, 1, 16, False, False, "tfim", True),  # one option only
-    (2, 3, 3, 256, True, True, "heis", True),    # bf16 d_h = 256: 32 / 16
+    (2, 3, 3, 256, True, True, "heis", True),    # bf16 d_h = 256: one option (48 rows)
 ]
 
 
