@@ -231,16 +231,24 @@ class Trainer:
         res.samples = int(res.energy.size) * self.ns
         return res
 
-    def evaluate(self, n_samples, batch=100000, seed=12345):
+    def evaluate(self, n_samples, batch=100000, seed=12345, precision=None):
         """Energy and variance of the trained state from n_samples fresh
         samples (Tables I and II use 10^6): (E, error bar of E, sigma^2,
-        error bar of sigma^2), error bars from the Gaussian assumption."""
+        error bar of sigma^2), error bars from the Gaussian assumption.
+        precision: evaluate the same parameters at another operand precision
+        (e.g. a BF16-trained state in FP32); default: the training one."""
+        m = self.m
+        if precision is not None:
+            k = dict(self.mkw)
+            k["precision"] = precision
+            m = V.model(dims=k["dims"], Lx=k["Lx"], Ly=k.get("Ly", 1), d_h=self.m.d_h,
+                        is_complex=k.get("is_complex", False), glu=k.get("glu", False), precision=precision)
         es = []
         k = 0
         while k < n_samples:
             b = min(batch, n_samples - k)
-            cfg, _, _ = V.rnn_sample(self.m, self.params, b, seed=seed, counter=k // batch)
-            e = V.local_energy(self.m, self.params, self.ham, cfg)
+            cfg, _, _ = V.rnn_sample(m, self.params, b, seed=seed, counter=k // batch)
+            e = V.local_energy(m, self.params, self.ham, cfg)
             es.append(e.cpu().numpy())
             k += b
         e = np.concatenate(es)
@@ -263,6 +271,8 @@ def _main():
     ap.add_argument("--d-final", type=int, default=256)
     ap.add_argument("--d-start", type=int, default=2)
     ap.add_argument("--steps", type=int, default=50000)
+    ap.add_argument("--stage-steps", type=int, default=0,
+                    help="adaptive: steps between doublings (the last width runs the rest); 0: equal stages")
     ap.add_argument("--ns", type=int, default=100)
     ap.add_argument("--lr", type=float, default=None,
                     help="learning rate (default 5e-4; early stopping: the rate from d_h = 64 on, default 1e-4)")
@@ -277,6 +287,8 @@ def _main():
     ap.add_argument("--complex", action="store_true")
     ap.add_argument("--bf16", action="store_true", help="BF16 MFMA operands")
     ap.add_argument("--eval-samples", type=int, default=10 ** 6)
+    ap.add_argument("--eval-fp32", action="store_true", help="evaluate the trained parameters with FP32 operands")
+    ap.add_argument("--check-every", type=int, default=500, help="steps between host reads of the history")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--quiet", action="store_true")
     a = ap.parse_args()
@@ -287,7 +299,11 @@ def _main():
         stages = static_stages(a.d_final, a.steps)
     elif a.mode == "adaptive":
         n_st = int(round(math.log2(a.d_final / a.d_start))) + 1
-        stages = adaptive_stages(a.d_start, a.d_final, a.steps // n_st)
+        stages = adaptive_stages(a.d_start, a.d_final, a.stage_steps or a.steps // n_st)
+        if a.stage_steps:
+            stages[-1].steps = a.steps - a.stage_steps * (n_st - 1)
+            if stages[-1].steps <= 0:
+                ap.error("--steps must exceed (number of widths - 1) x --stage-steps")
     else:
         # early stopping (Table III): 0.01 below d_h = 64, 1e-4 from d_h = 64 on
         hi = V.adam_cfg(lr0=a.lr_first if a.lr_first is not None else 1e-2, **decay)
@@ -303,14 +319,18 @@ def _main():
     model = dict(dims=2 if two_d else 1, Lx=a.N, Ly=a.Ly, is_complex=a.complex, glu=two_d,
                  precision=V.VMC_BF16 if a.bf16 else V.VMC_FP32)
     tr = Trainer(model, H, a.ns, stages, adam, seed=a.seed)
-    res = tr.run(log=None if a.quiet else (lambda s: print(s, flush=True)))
+    res = tr.run(check_every=a.check_every, log=None if a.quiet else (lambda s: print(s, flush=True)))
     n_sites = a.N * a.Ly
     out = dict(ham=a.ham, N=a.N, Ly=a.Ly, mode=a.mode, stages=[s.d_h for s in stages], stage_steps=res.stage_steps,
                ns=a.ns, train_wall_s=round(res.wall_s, 2), train_samples_per_s=round(res.samples / res.wall_s, 1),
                ms_per_step=round(1e3 * res.wall_s / max(1, res.energy.size), 4),
-               last_energy_mean_1000=float(res.energy[-1000:].mean()))
+               last_energy_mean_1000=float(res.energy[-1000:].mean()),
+               stage_end_energy=[float(res.energy[:e][-min(100, n):].mean())
+                                 for e, n in zip(np.cumsum(res.stage_steps), res.stage_steps)],
+               precision="bf16" if a.bf16 else "fp32")
     if a.eval_samples > 0:
-        E, dE, var, dvar = tr.evaluate(a.eval_samples)
+        E, dE, var, dvar = tr.evaluate(a.eval_samples, precision=V.VMC_FP32 if a.eval_fp32 else None)
+        out["eval_precision"] = "fp32" if (a.eval_fp32 or not a.bf16) else "bf16"
         out.update(energy=E, energy_err=dE, var_per_spin=var / n_sites, var_per_spin_err=dvar / n_sites,
                    eval_samples=a.eval_samples)
     print(json.dumps(out), flush=True)
