@@ -94,6 +94,18 @@ def adaptive_stages(d_start, d_final, steps_per_stage):
     return out
 
 
+def interval_stages(d_start, d_final, total_steps, interval):
+    """Widths doubling every `interval` steps from d_start to d_final; the
+    last width runs the rest of total_steps (Sec. III: the 1D, long-range and
+    cluster Adaptive runs double at a fixed step count)."""
+    out = adaptive_stages(d_start, d_final, interval)
+    rest = total_steps - interval * (len(out) - 1)
+    if rest <= 0:
+        raise ValueError("total_steps must exceed (number of widths - 1) x interval")
+    out[-1].steps = rest
+    return out
+
+
 @dataclass
 class TrainResult:
     energy: np.ndarray = field(default_factory=lambda: np.zeros(0))      # Re E per step
@@ -299,11 +311,11 @@ def _main():
         stages = static_stages(a.d_final, a.steps)
     elif a.mode == "adaptive":
         n_st = int(round(math.log2(a.d_final / a.d_start))) + 1
-        stages = adaptive_stages(a.d_start, a.d_final, a.stage_steps or a.steps // n_st)
-        if a.stage_steps:
-            stages[-1].steps = a.steps - a.stage_steps * (n_st - 1)
-            if stages[-1].steps <= 0:
-                ap.error("--steps must exceed (number of widths - 1) x --stage-steps")
+        try:
+            stages = (interval_stages(a.d_start, a.d_final, a.steps, a.stage_steps) if a.stage_steps
+                      else adaptive_stages(a.d_start, a.d_final, a.steps // n_st))
+        except ValueError as e:
+            ap.error(str(e))
     else:
         # early stopping (Table III): 0.01 below d_h = 64, 1e-4 from d_h = 64 on
         hi = V.adam_cfg(lr0=a.lr_first if a.lr_first is not None else 1e-2, **decay)

@@ -78,3 +78,24 @@ def test_early_stopping_stages():
     # each stage ran at least one full window plus the patience, and stopped at a check boundary
     assert all(25 <= s <= 400 and s % 20 == 0 for s in res.stage_steps)
     assert tr.t_dev.item() == sum(res.stage_steps)
+
+
+def test_evaluate_at_fp32_equals_an_fp32_model():
+    """evaluate(precision=FP32) on a BF16 model samples and scores the same
+    parameters exactly as a model built at FP32 does (the evaluation of
+    BF16-trained states in FP32)."""
+    torch = torch_gpu()
+    from paper_2507_18700_amd import vmcrnn as V
+    from paper_2507_18700_amd.train import Trainer, static_stages
+    H = V.ham(V.VMC_HEISENBERG, J=1.0, h=0.0, marshall=True)
+    kw = dict(dims=2, Lx=3, Ly=3, glu=True)
+    a = Trainer(dict(kw, precision=V.VMC_BF16), H, 64, static_stages(32, 4), V.adam_cfg(lr0=1e-3), seed=5)
+    a.run(check_every=4)
+    b = Trainer(dict(kw, precision=V.VMC_FP32), H, 64, static_stages(32, 0), V.adam_cfg(lr0=1e-3), seed=5)
+    b.params.copy_(a.params)
+    ra = a.evaluate(3000, batch=1000, precision=V.VMC_FP32)
+    rb = b.evaluate(3000, batch=1000)
+    rc = a.evaluate(3000, batch=1000)
+    assert ra == rb
+    assert ra != rc and abs(ra[0] - rc[0]) < 1e-2 * abs(ra[0])
+

@@ -3,7 +3,9 @@ the moving average of the energy variance (App. B) and the stage lists of
 the Static and Adaptive schedules.  CPU only."""
 import math
 
-from paper_2507_18700_amd.train import EarlyStop, EarlyStopState, adaptive_stages, static_stages
+import pytest
+
+from paper_2507_18700_amd.train import EarlyStop, EarlyStopState, adaptive_stages, interval_stages, static_stages
 
 
 def test_delta_of_the_hidden_width():
@@ -41,3 +43,15 @@ def test_stage_lists():
     st = static_stages(256, 50000)
     assert len(st) == 1 and st[0].d_h == 256 and st[0].steps == 50000
     assert math.isclose(sum(s.steps for s in adaptive_stages(32, 256, 50000)), 200000)
+
+
+def test_interval_stages():
+    """Doubling every 200 steps over 2000 (the long-range TFIM run): eight
+    widths 2..256, the last one taking the remaining 600 steps."""
+    st = interval_stages(2, 256, 2000, 200)
+    assert [x.d_h for x in st] == [2, 4, 8, 16, 32, 64, 128, 256]
+    assert [x.steps for x in st] == [200] * 7 + [600]
+    assert sum(x.steps for x in st) == 2000
+    with pytest.raises(ValueError):
+        interval_stages(2, 256, 1400, 200)
+
