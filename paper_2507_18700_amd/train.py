@@ -31,13 +31,15 @@ from . import vmcrnn as V
 @dataclass
 class EarlyStop:
     """Early stopping on the moving average (window `window`) of the energy
-    variance per spin: an improvement is a drop of the average below the best
-    value so far by more than delta(d_h) = 10^(-log2(d_h)/2) (App. B); the
-    criterion fires after `patience` steps without improvement, counted from
-    the first step with a full window."""
+    variance sigma^2 (per_spin: sigma^2 / N): an improvement is a drop of the
+    average below the best value so far by more than
+    delta(d_h) = 10^(-log2(d_h)/2) (App. B); the criterion fires after
+    `patience` steps without improvement, counted from the first step with a
+    full window."""
     window: int = 500
     patience: int = 10000
     max_steps_per_stage: int = 10 ** 7
+    per_spin: bool = False
 
     @staticmethod
     def delta(d_h):
@@ -55,16 +57,22 @@ class EarlyStopState:
         self.best = math.inf
         self.wait = 0
         self.fired_at = None
+        self.wsum = 0.0  # running sum of the last `window` values
 
-    def update(self, var_per_spin):
+    def update(self, variances):
         """Feed the per-step variances (in order); returns the index (within
         the stage) of the step at which the criterion fired, or None."""
         w = self.rule.window
-        for v in var_per_spin:
+        for v in variances:
             self.vals.append(float(v))
-            if self.fired_at is not None or len(self.vals) < w:
+            n = len(self.vals)
+            if n % 10000 == 0:  # exact sum now and then, so that rounding does not drift
+                self.wsum = math.fsum(self.vals[-w:])
+            else:
+                self.wsum += self.vals[-1] - (self.vals[-1 - w] if n > w else 0.0)
+            if self.fired_at is not None or n < w:
                 continue
-            avg = sum(self.vals[-w:]) / w
+            avg = self.wsum / w
             if avg < self.best - self.delta:
                 self.best = avg
                 self.wait = 0
@@ -126,7 +134,7 @@ class Trainer:
     stages with steps = 0."""
 
     def __init__(self, model, ham, ns, stages, adam, seed=0, sample_seed=1, noise_std=1e-3, grow_seed=2,
-                 early_stop=None, init_params=None, graph=True, device="cuda"):
+                 early_stop=None, init_params=None, graph=True, device="cuda", restart_adam=False):
         self.mkw = dict(model)
         self.ham = ham
         self.ns = ns
@@ -138,6 +146,7 @@ class Trainer:
         self.grow_seed = grow_seed
         self.early_stop = early_stop or EarlyStop()
         self.graph = graph
+        self.restart_adam = restart_adam
         self.dev = torch.device(device)
         d0 = stages[0].d_h
         self.m = self._model(d0)
@@ -161,6 +170,10 @@ class Trainer:
         p, mm, vv, to = V.grow_hidden(self.m, self.params, new_dh, self.grow_seed + new_dh, self.noise_std,
                                       self.mom_m, self.mom_v)
         self.params, self.mom_m, self.mom_v, self.m = p, mm, vv, to
+        if self.restart_adam:  # a fresh optimiser state for the new width (moments 0, step count 0)
+            self.mom_m.zero_()
+            self.mom_v.zero_()
+            self.t_dev.zero_()
 
     def _stage_buffers(self, hist_len):
         ns, m, dev = self.ns, self.m, self.dev
@@ -231,7 +244,7 @@ class Trainer:
                 if log:
                     log("d_h %d step %d/%s E %.8f var/N %.3e" % (st.d_h, done, budget if fixed else "-",
                                                                  h[-1, 0], h[-1, 2] / N))
-                if es is not None and es.update(h[:, 2] / N) is not None:
+                if es is not None and es.update(h[:, 2] / N if self.early_stop.per_spin else h[:, 2]) is not None:
                     break
             res.stage_steps.append(done)
             del graph
@@ -301,6 +314,11 @@ def _main():
     ap.add_argument("--eval-samples", type=int, default=10 ** 6)
     ap.add_argument("--eval-fp32", action="store_true", help="evaluate the trained parameters with FP32 operands")
     ap.add_argument("--check-every", type=int, default=500, help="steps between host reads of the history")
+    ap.add_argument("--patience", type=int, default=10000, help="early stopping: steps without improvement")
+    ap.add_argument("--max-stage-steps", type=int, default=10 ** 7, help="early stopping: cap per width")
+    ap.add_argument("--stop-per-spin", action="store_true", help="early stopping on sigma^2/N instead of sigma^2")
+    ap.add_argument("--restart-adam", action="store_true",
+                    help="fresh Adam state at each width change instead of the carried (zero-padded) one")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--quiet", action="store_true")
     a = ap.parse_args()
@@ -330,7 +348,9 @@ def _main():
     two_d = a.Ly > 1
     model = dict(dims=2 if two_d else 1, Lx=a.N, Ly=a.Ly, is_complex=a.complex, glu=two_d,
                  precision=V.VMC_BF16 if a.bf16 else V.VMC_FP32)
-    tr = Trainer(model, H, a.ns, stages, adam, seed=a.seed)
+    tr = Trainer(model, H, a.ns, stages, adam, seed=a.seed,
+                 early_stop=EarlyStop(patience=a.patience, max_steps_per_stage=a.max_stage_steps,
+                                      per_spin=a.stop_per_spin), restart_adam=a.restart_adam)
     res = tr.run(check_every=a.check_every, log=None if a.quiet else (lambda s: print(s, flush=True)))
     n_sites = a.N * a.Ly
     out = dict(ham=a.ham, N=a.N, Ly=a.Ly, mode=a.mode, stages=[s.d_h for s in stages], stage_steps=res.stage_steps,

@@ -99,3 +99,27 @@ def test_evaluate_at_fp32_equals_an_fp32_model():
     assert ra == rb
     assert ra != rc and abs(ra[0] - rc[0]) < 1e-2 * abs(ra[0])
 
+
+def test_restart_adam_at_each_width():
+    """restart_adam: after a doubling the moments are zero and the step
+    count restarts, so that at the end the count equals the last stage's
+    steps; without it the count runs on over the stages."""
+    torch = torch_gpu()
+    from paper_2507_18700_amd import vmcrnn as V
+    from paper_2507_18700_amd.train import Trainer, adaptive_stages
+    H = V.ham(V.VMC_TFIM, J=1.0, h=1.0)
+    counts = []
+    for restart in (True, False):
+        tr = Trainer(dict(dims=1, Lx=8), H, 32, adaptive_stages(4, 8, 6), V.adam_cfg(lr0=1e-2),
+                     restart_adam=restart)
+        tr.stages = tr.stages[:1]
+        tr.run(check_every=3)
+        tr._grow(8)
+        torch.cuda.synchronize()
+        if restart:
+            assert not tr.mom_m.any() and not tr.mom_v.any()
+        else:
+            assert tr.mom_m.any() and tr.mom_v.any()
+        counts.append(tr.t_dev.item())
+    assert counts == [0, 6]
+
