@@ -64,6 +64,8 @@ __device__ inline void rebase_bwd(BwdArgs &a, const BatchInfo &b, int k) {
 // two 16-unit blocks per wave) hold the transposed weights; one such
 // workgroup fills a compute unit, so the tile is sized to spread the usual
 // sample counts over the chip in one round (48 rows at d_h = 128).
+constexpr int kXcdsB = 8;  // XCDs of the chip (work-groups are dealt to them round-robin by id)
+
 #define BWD_MT(DH) ((DH) == 128 ? 48 : (DH) >= 256 ? 32 : 64)
 #define BWD_NW(DH) ((DH) >= 128 ? 8 : 4)
 
@@ -111,10 +113,20 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a0, BatchInfo bi) {
     const int l16 = lane & 15, lq = lane >> 4;
     // batched: one problem per group of bi.tiles work-groups
     BwdArgs a = a0;
-    int tile = blockIdx.x;
+    // Work-groups go to the XCDs round-robin by id; neighbouring tiles share
+    // the 128-byte lines of the transposed arrays (a tile is not a multiple
+    // of 64 samples), so each XCD takes a contiguous run of tiles and a
+    // shared line stays in one L2.
+    int tile;
+    {
+        // XCD y takes G/8 tiles, plus one if y < G % 8
+        const int G = gridDim.x, b = blockIdx.x, x = b % kXcdsB;
+        const int q = G / kXcdsB, r = G - q * kXcdsB;
+        tile = __builtin_amdgcn_readfirstlane(x * q + min(x, r) + b / kXcdsB);
+    }
     if (BATCH) {
-        const int k = blockIdx.x / bi.tiles;
-        tile = blockIdx.x - k * bi.tiles;
+        const int k = tile / bi.tiles;
+        tile -= k * bi.tiles;
         rebase_bwd(a, bi, k);
     }
     const int N = a.d.N, Lx = a.d.Lx, Ly = a.d.Ly;

@@ -446,16 +446,30 @@ static int dw_mf(int MD) {
 static int dw_tiles_m(const SegDims &s) { return (s.MD + 128 * dw_mf(s.MD) - 1) / (128 * dw_mf(s.MD)); }
 static int dw_tiles_n(const SegDims &s) { return (s.K + 5 + DW_COLS - 1) / DW_COLS; }
 
-// Sample chunks per position of the weight-gradient contraction: about 768
-// work-groups in all (three rounds of the chip), chunks of >= 1024 samples,
-// at most 16.
+// Resident work-groups per CU of dw_mfma<P, MF> on gfx950 (8 waves each; the
+// register use of 1, 2 and 3 fragments per wave allows 6, 4 and 2 waves per
+// SIMD), and the CUs of the chip.
+static int dw_wg_per_cu(int mf) { return mf >= 3 ? 1 : mf == 2 ? 2 : 3; }
+constexpr int kDwCUs = 256;
+
+// Sample chunks per position of the weight-gradient contraction: chunks of
+// >= 1024 samples, at most 16, and among those the count with the least
+// time in rounds of the chip per sample, ceil(W / R) / c for W = tiles * c
+// work-groups of which R are resident at once (the smallest such count).
 static int dw_chunks(const Dims &d, const SegDims &s, int64_t nsp) {
     const int64_t tiles = (int64_t)dw_tiles_m(s) * dw_tiles_n(s) * d.N;
-    int64_t c = (768 + tiles - 1) / tiles;
-    const int64_t cmax = nsp / 1024 > 1 ? nsp / 1024 : 1;
-    if (c > cmax) c = cmax;
-    if (c > 16) c = 16;
-    return (int)(c < 1 ? 1 : c);
+    const int64_t R = (int64_t)kDwCUs * dw_wg_per_cu(dw_mf(s.MD));
+    int64_t cmax = nsp / 1024 > 1 ? nsp / 1024 : 1;
+    if (cmax > 16) cmax = 16;
+    int64_t best = 1, best_rounds = (tiles + R - 1) / R;
+    for (int64_t c = 2; c <= cmax; c++) {
+        const int64_t rounds = (tiles * c + R - 1) / R;
+        if (rounds * best < best_rounds * c) {  // rounds / c < best_rounds / best
+            best = c;
+            best_rounds = rounds;
+        }
+    }
+    return (int)best;
 }
 
 void grad_sizes(const Dims &d, int64_t ns, size_t *part_floats) {
