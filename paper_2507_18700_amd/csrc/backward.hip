@@ -36,7 +36,7 @@ struct BwdArgs {
     const double *eloc, *w, *stats;
     const float *coef_lp, *coef_ph;  // given coefficients a_s, b_s (then eloc, w, stats are unused)
     void *dtc, *dtg, *dth;  // transposed deltas: cell [N][NDC][nsp], GLU [N][2DH][nsp], heads [N][4][nsp]
-    float *dcol;            // [grid][Lx][MT][DH]
+    float *dcol;            // [grid][Lx][DH][MT]
 };
 
 // Arguments of the reverse sweep for problem k of a batch (see BatchInfo):
@@ -409,23 +409,47 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a0, BatchInfo bi) {
         }
         float4 fhp[DIMS == 1 ? RB : 1][DIMS == 1 ? UB : 1];  // 1D: h_{n-1} (FP32)
         if (DIMS == 1) {
+            // every load first (rows past ns read row ns - 1), then the rows past
+            // ns zeroed: the loads are in flight together, with no per-lane branch
+            float hv[DIMS == 1 ? RB : 1][DIMS == 1 ? UB : 1][4];
 #pragma unroll
             for (int rb = 0; rb < RB; rb++)
 #pragma unroll
                 for (int ub = 0; ub < UB; ub++) {
-                    float hv[4] = {0.f, 0.f, 0.f, 0.f};
                     const int64_t s0 = srow0(rb);
-                    if (q > 0) {
-                        const float *hp = a.hcache + ((int64_t)(q - 1) * ns + s0) * DH + wu * C::UW + ub * 16 + l16;
+                    const float *hp = a.hcache + (int64_t)(q > 0 ? q - 1 : 0) * ns * DH + wu * C::UW + ub * 16 + l16;
 #pragma unroll
-                        for (int ii = 0; ii < 4; ii++)
-                            if (s0 + ii < ns) hv[ii] = hp[(int64_t)ii * DH];
-                    }
-                    fhp[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)] = make_float4(hv[0], hv[1], hv[2], hv[3]);
+                    for (int ii = 0; ii < 4; ii++)
+                        hv[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)][ii] =
+                            hp[(s0 + ii < ns ? s0 + ii : ns - 1) * DH];
+                }
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    const int64_t s0 = srow0(rb);
+                    float v[4];
+#pragma unroll
+                    for (int ii = 0; ii < 4; ii++)
+                        v[ii] = (q > 0 && s0 + ii < ns) ? hv[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)][ii] : 0.f;
+                    fhp[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)] = make_float4(v[0], v[1], v[2], v[3]);
                 }
         }
 
-        // (d) total dh and the gate deltas
+        // (d) total dh and the gate deltas; the dh parked by the vertical
+        // successor (2D) is read as one float4 per row block, every load issued
+        // before the first use (positions without a parked value discard it)
+        float4 dpk[DIMS == 2 ? RB : 1][DIMS == 2 ? UB : 1];
+        if (DIMS == 2) {
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+                for (int ub = 0; ub < UB; ub++) {
+                    const int u = wu * C::UW + ub * 16 + l16, r0 = wr * C::RW + rb * 16 + 4 * lq;
+                    dpk[rb % (DIMS == 2 ? RB : 1)][ub % (DIMS == 2 ? UB : 1)] =
+                        *(const float4 *)&dcol[((int64_t)icol * DH + u) * MT + r0];
+                }
+        }
         float direct[RB][UB][4];
 #pragma unroll
         for (int rb = 0; rb < RB; rb++) {
@@ -448,7 +472,11 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a0, BatchInfo bi) {
                 for (int ii = 0; ii < 4; ii++) {
                     const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
                     float dh = (glu ? accg[rb][ub][ii] : dgv[rb][ub][ii]) + carry[rb][ub][ii];
-                    if (vt_succ_parked) dh += dcol[((int64_t)icol * MT + r) * DH + u];
+                    if (DIMS == 2) {
+                        const float4 pk = dpk[rb % (DIMS == 2 ? RB : 1)][ub % (DIMS == 2 ? UB : 1)];
+                        const float pv = ii == 0 ? pk.x : ii == 1 ? pk.y : ii == 2 ? pk.z : pk.w;
+                        dh += vt_succ_parked ? pv : 0.f;
+                    }
                     float g0, g1, g2, g3 = 0.f;
                     if (DIMS == 1) {
                         // h' = (1-u) h + u c, c = tanh(r m + x-term)
@@ -539,22 +567,19 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a0, BatchInfo bi) {
 #pragma unroll
         for (int rb = 0; rb < RB; rb++)
 #pragma unroll
-            for (int ii = 0; ii < 4; ii++) {
-                const int r = wr * C::RW + rb * 16 + 4 * lq + ii;
+            for (int ub = 0; ub < UB; ub++) {
+                const int u = wu * C::UW + ub * 16 + l16, r0 = wr * C::RW + rb * 16 + 4 * lq;
+                if (DIMS == 1) {
 #pragma unroll
-                for (int ub = 0; ub < UB; ub++) {
-                    const int u = wu * C::UW + ub * 16 + l16;
-                    if (DIMS == 1) {
-                        carry[rb][ub][ii] = accx[rb][ub][ii] + direct[rb][ub][ii];
-                    } else {
-                        const float dhz = accx[rb][ub][ii], dvt = accx[rb][UB + ub][ii];
-                        if (row_start) {
-                            carry[rb][ub][ii] = has_vt ? dvt : 0.f;
-                        } else {
-                            carry[rb][ub][ii] = dhz;
-                            if (has_vt) dcol[((int64_t)icol * MT + r) * DH + u] = dvt;
-                        }
-                    }
+                    for (int ii = 0; ii < 4; ii++) carry[rb][ub][ii] = accx[rb][ub][ii] + direct[rb][ub][ii];
+                } else {
+#pragma unroll
+                    for (int ii = 0; ii < 4; ii++)
+                        carry[rb][ub][ii] = row_start ? (has_vt ? accx[rb][UB + ub][ii] : 0.f) : accx[rb][ub][ii];
+                    if (!row_start && has_vt)
+                        *(float4 *)&dcol[((int64_t)icol * DH + u) * MT + r0] =
+                            make_float4(accx[rb][UB + ub][0], accx[rb][UB + ub][1], accx[rb][UB + ub][2],
+                                        accx[rb][UB + ub][3]);
                 }
             }
         __syncthreads();

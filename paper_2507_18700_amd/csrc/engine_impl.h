@@ -361,19 +361,24 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
 
     bool first = true;
     int cur_prob = -1;  // batched chain launch: the problem whose state setup() loaded
+    // chain launches: thread 0 claims the next tile from the queue while the
+    // current one runs (a claimed tile is always run: the loop ends only on a
+    // claim past the last tile)
+    int claim = 0;
     for (;;) {
         // ---------------------------------------------------------- tile
         int p = -1, nrow;
         int64_t e0;
         if (CHAIN && BATCH) {
             __syncthreads();
-            if (tid == 0) sTile = atomicAdd(a0.tile_counter, 1);
+            if (tid == 0) sTile = first ? atomicAdd(a0.tile_counter, 1) : claim;
             __syncthreads();
             // one queue over the tiles of every problem, longest chains first:
             // the entry (first tile, problem, position) that holds tile t
             const int t = __builtin_amdgcn_readfirstlane(sTile);
             const auto *sc = kconst((const int *)bi.sched);
             if (t >= sc[4 * bi.nsched]) break;
+            if (tid == 0) claim = atomicAdd(a0.tile_counter, 1);
             int lo = 0, hi = bi.nsched - 1;
             while (lo < hi) {
                 int mid = (lo + hi + 1) >> 1;
@@ -392,13 +397,14 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
             nrow = (int)min((int64_t)MT, (int64_t)kconst(a.cnt)[p] - e0);
         } else if (CHAIN) {
             __syncthreads();
-            if (tid == 0) sTile = atomicAdd(a.tile_counter, 1);
+            if (tid == 0) sTile = first ? atomicAdd(a.tile_counter, 1) : claim;
             __syncthreads();
             // uniform across the work-group: the position loop, its table reads
             // and branches then run on the scalar unit
             const int t = __builtin_amdgcn_readfirstlane(sTile);
             const auto *ts = kconst(a.tile_start);
             if (t >= ts[N]) break;
+            if (tid == 0) claim = atomicAdd(a.tile_counter, 1);
             int lo = 0, hi = N - 1;  // largest p with tile_start[p] <= t
             while (lo < hi) {
                 int mid = (lo + hi + 1) >> 1;
@@ -438,10 +444,26 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
             sAcc[tid] = make_double2(0.0, 0.0);
         }
         __syncthreads();
-        for (int e = tid; e < MT * N; e += NT) {
-            const int r = e / N, c = e - r * N;
-            const int s = sRow[r];
-            sSig[e] = (s >= 0 && TF) ? a.cfg_in[(int64_t)s * N + c] : (uint8_t)0;
+        if (TF) {
+            // eight loads per thread in flight together (an absent row reads row 0
+            // and is zeroed), then the stores
+            constexpr int BQ = 8;
+            const int tot = MT * N;
+            for (int eb = tid; eb < tot; eb += BQ * NT) {
+                uint8_t v[BQ];
+#pragma unroll
+                for (int j = 0; j < BQ; j++) {
+                    const int e = min(eb + j * NT, tot - 1), r = e / N, c = e - r * N;
+                    const int s = sRow[r];
+                    v[j] = a.cfg_in[(int64_t)(s >= 0 ? s : 0) * N + c];
+                    v[j] = s >= 0 ? v[j] : (uint8_t)0;
+                }
+#pragma unroll
+                for (int j = 0; j < BQ; j++)
+                    if (eb + j * NT < tot) sSig[eb + j * NT] = v[j];
+            }
+        } else {
+            for (int e = tid; e < MT * N; e += NT) sSig[e] = 0;
         }
         __syncthreads();
         if (tid < MT && my_s >= 0 && CHAIN) {
@@ -458,12 +480,16 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
 #pragma unroll
                 for (int i = 0; i < 4; i++) hreg[rb][ub][i] = 0.f;
         if (p >= 0) {
-            for (int e = tid; e < NCH; e += NT) {
+            // every load first (an absent row reads row 0 and is zeroed), then
+            // the LDS stores
+            uint4 hv[PF];
+#pragma unroll
+            for (int i = 0; i < PF; i++) {
+                const int e = min(tid + i * NT, NCH - 1);
                 const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
                 const int s = sRow[r];
-                uint4 v = make_uint4(0, 0, 0, 0);
-                if (s >= 0) v = *(const uint4 *)&hcs[((int64_t)p * ns_c + s) * DH + c];
-                *(uint4 *)&sH[p & 1][r * H_LD + c] = v;
+                hv[i] = *(const uint4 *)&hcs[((int64_t)p * ns_c + (s >= 0 ? s : 0)) * DH + c];
+                if (s < 0) hv[i] = make_uint4(0, 0, 0, 0);
             }
             if (DIMS == 1) {
 #pragma unroll
@@ -471,14 +497,22 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
                     const int s = sRow[wr * C::RW + rb * 16 + l16];
 #pragma unroll
                     for (int ub = 0; ub < UB; ub++) {
-                        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                        if (s >= 0) v = *(const float4 *)&a.hcache[((int64_t)p * ns_c + s) * DH + unit0(ub)];
+                        float4 v = *(const float4 *)&a.hcache[((int64_t)p * ns_c + (s >= 0 ? s : 0)) * DH + unit0(ub)];
+                        if (s < 0) v = make_float4(0.f, 0.f, 0.f, 0.f);
                         float *hr = hreg[rb % (DIMS == 1 ? RB : 1)][ub % (DIMS == 1 ? UB : 1)];
                         hr[0] = v.x;
                         hr[1] = v.y;
                         hr[2] = v.z;
                         hr[3] = v.w;
                     }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < PF; i++) {
+                const int e = tid + i * NT;
+                if (e < NCH) {
+                    const int r = e / (DH / VEC), c = (e % (DH / VEC)) * VEC;
+                    *(uint4 *)&sH[p & 1][r * H_LD + c] = hv[i];
                 }
             }
         }
