@@ -18,12 +18,12 @@ namespace vmc {
 
 constexpr int DW_TILE = 128;            // padding granule of the weight-gradient partials
 constexpr int DW_NF = 9, DW_COLS = 144;  // input-column fragments / columns per contraction tile
-// MFMA k-steps per pipeline step of the contraction: two for the 3-fragment
+// MFMA k-steps per pipeline step of the contraction: three for the 3-fragment
 // tiles (one work-group per compute unit by registers, so the step size sets
 // the bytes in flight); one for the smaller tiles, which keep two or more
 // work-groups per compute unit that way
 template <int MF>
-constexpr int dw_sub() { return MF == 3 ? 2 : 1; }
+constexpr int dw_sub() { return MF == 3 ? 3 : 1; }
 
 // ------------------------------------------------------------- statistics
 
