@@ -302,7 +302,13 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a0, BatchInfo bi) {
                 for (int ub = 0; ub < UB; ub++)
                     dgv[rb][ub][ii] = hw[0][ub] * dl.x + hw[1][ub] * dl.y + hw[2][ub] * dl.z + hw[3][ub] * dl.w;
             }
-            if (glu) {
+        }
+        // (the GLU test outside the row-block loop: inside it, the path that skips
+        // the GLU part would leave the pre-activation loads pending, and every row
+        // block would then wait for all earlier stores before reading them)
+        if (glu) {
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++) {
                 const int64_t s0 = srow0(rb);
 #pragma unroll
                 for (int ub = 0; ub < UB; ub++) {
