@@ -252,15 +252,28 @@ __global__ void conn_list(int ham_kind, const uint8_t *cfg, int64_t ns, int Lx, 
 }
 
 // Tiles per position, longest suffix (smallest p) first.
-__global__ void tile_scan(int N, int MT, const int *cnt, int *tile_start) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int t = 0;
-        for (int p = 0; p < N; p++) {
-            tile_start[p] = t;
-            t += (cnt[p] + MT - 1) / MT;
-        }
-        tile_start[N] = t;
+__global__ __launch_bounds__(256) void tile_scan(int N, int MT, const int *cnt, int *tile_start) {
+    // each thread a contiguous run of positions, then an exclusive scan of the
+    // per-thread tile counts in LDS (the loads of all threads in flight at once)
+    __shared__ int part[256];
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int per = (N + NT - 1) / NT, p0 = min(N, tid * per), p1 = min(N, p0 + per);
+    int sum = 0;
+    for (int p = p0; p < p1; p++) sum += (cnt[p] + MT - 1) / MT;
+    part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < NT; o <<= 1) {
+        const int v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
     }
+    int t = part[tid] - sum;
+    for (int p = p0; p < p1; p++) {
+        tile_start[p] = t;
+        t += (cnt[p] + MT - 1) / MT;
+    }
+    if (tid == NT - 1) tile_start[N] = part[NT - 1];
 }
 
 // One queue over the chain tiles of a batch, longest chains first.  The
@@ -457,7 +470,7 @@ hipError_t launch_sched(int ham_kind, int Lx, int Ly, int64_t ns, const uint8_t 
         if (grid < 1) grid = 1;
         hipLaunchKernelGGL(conn_list, dim3(grid), dim3(256), 0, st, ham_kind, cfg, ns, Lx, Ly, cnt, list_off, list);
     }
-    hipLaunchKernelGGL(tile_scan, dim3(1), dim3(64), 0, st, Lx * Ly, MT, cnt, tile_start);
+    hipLaunchKernelGGL(tile_scan, dim3(1), dim3(256), 0, st, Lx * Ly, MT, cnt, tile_start);
     return hipGetLastError();
 }
 
