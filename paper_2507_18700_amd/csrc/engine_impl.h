@@ -92,6 +92,8 @@ struct Eng {
         (XT ? 4 * ((size_t)NXG * NXC * XT_LD + 2 * MT) : 16);  // (+ the LDS constants of streamed weights)
 };
 
+constexpr int kXcdsE = 8;  // XCDs of the chip
+
 // Read-only tables written by earlier launches (position table, tile
 // schedule): through the constant address space, so that reads at uniform
 // indices become scalar loads.
@@ -182,10 +184,19 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
     // problem per group of `bi.tiles` work-groups; the batched chain launch
     // rebases per tile)
     FwdArgs a = a0;
+    // row launches: work-groups go to the XCDs round-robin by id, and a tile
+    // that is not a multiple of 64 rows shares 128-byte lines of the
+    // [unit][sample] activation arrays with its neighbours, so each XCD takes
+    // a contiguous run of tiles (XCD x: G/8 tiles, plus one if x < G % 8)
     int row_tile = blockIdx.x;
+    if (!CHAIN) {
+        const int G = gridDim.x, b = blockIdx.x, x = b % kXcdsE;
+        const int q = G / kXcdsE, rm = G - q * kXcdsE;
+        row_tile = __builtin_amdgcn_readfirstlane(x * q + min(x, rm) + b / kXcdsE);
+    }
     if (BATCH && !CHAIN) {
-        const int k = blockIdx.x / bi.tiles;
-        row_tile = blockIdx.x - k * bi.tiles;
+        const int k = row_tile / bi.tiles;
+        row_tile -= k * bi.tiles;
         rebase_fwd(a, bi, k);
     }
     const int cplx = CPX >= 0 ? CPX : a.d.cplx, glu = a.d.glu;
