@@ -207,7 +207,9 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a0, BatchInfo bi) {
             if constexpr (VEC == 4) return make_float4(0.f, 0.f, 0.f, 0.f);
             else return make_uint2(0u, 0u);
         }
-        return *(const RawF *)((const T *)a.act + ((int64_t)q * NF * DH + f * DH + u) * nsp + s0);
+        // [position][16-sample block][feature][16] (the forward's layout)
+        return *(const RawF *)((const T *)a.act + (int64_t)q * NF * DH * nsp + (s0 >> 4) * (NF * DH * 16) +
+                               (f * DH + u) * 16 + (s0 & 15));
     };
     auto widen = [](RawF v) -> float4 {
         if constexpr (VEC == 4) {

@@ -659,13 +659,17 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
                     }
                     const int64_t sx = e0 + r;
                     if (store_act && sx < a.nsp) {
+                        // [position][16-sample block][feature][16]: the 4 units of
+                        // a lane are adjacent 16-sample rows, so the 4 stores of a
+                        // wave fill whole 128-byte lines
+                        T *hb = (T *)a.hT + (int64_t)qc * DH * a.nsp + (sx >> 4) * (DH * 16) + (sx & 15);
+                        T *ab = (T *)a.act + (int64_t)qc * (NA + 2) * DH * a.nsp + (sx >> 4) * ((NA + 2) * DH * 16) +
+                                (sx & 15);
 #pragma unroll
                         for (int i = 0; i < 4; i++) {
-                            ((T *)a.hT)[((int64_t)qc * DH + u0 + i) * a.nsp + sx] = cvt<P>(hq[i]);
+                            hb[(u0 + i) * 16] = cvt<P>(hq[i]);
 #pragma unroll
-                            for (int f = 0; f < NA; f++)
-                                ((T *)a.act)[((int64_t)qc * (NA + 2) * DH + f * DH + u0 + i) * a.nsp + sx] =
-                                    cvt<P>(gv[STORE ? f : 0][i]);
+                            for (int f = 0; f < NA; f++) ab[(f * DH + u0 + i) * 16] = cvt<P>(gv[STORE ? f : 0][i]);
                         }
                     }
                 }
@@ -689,14 +693,17 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
                 head_part(ub, g, p0, p1, p2, p3);
                 const int64_t sx = e0 + r;
                 if (store_act && sx < a.nsp) {
+                    // (the same 16-sample blocked layout as the cell's arrays)
                     const bool ok = s >= 0;
                     const int u0 = unit0(ub);
+                    T *gb = (T *)a.gT + (int64_t)qg * DH * a.nsp + (sx >> 4) * (DH * 16) + (sx & 15);
+                    T *ab = (T *)a.act + (int64_t)qg * (NA + 2) * DH * a.nsp + (sx >> 4) * ((NA + 2) * DH * 16) +
+                            (sx & 15);
 #pragma unroll
                     for (int i = 0; i < 4; i++) {
-                        ((T *)a.gT)[((int64_t)qg * DH + u0 + i) * a.nsp + sx] = cvt<P>(ok ? g[i] : 0.f);
-                        T *fa = (T *)a.act + ((int64_t)qg * (NA + 2) * DH + NA * DH + u0 + i) * a.nsp + sx;
-                        fa[0] = cvt<P>(ok ? a1[i] : 0.f);
-                        fa[(int64_t)DH * a.nsp] = cvt<P>(ok ? a2[i] : 0.f);
+                        gb[(u0 + i) * 16] = cvt<P>(ok ? g[i] : 0.f);
+                        ab[(NA * DH + u0 + i) * 16] = cvt<P>(ok ? a1[i] : 0.f);
+                        ab[((NA + 1) * DH + u0 + i) * 16] = cvt<P>(ok ? a2[i] : 0.f);
                     }
                 }
             }

@@ -123,10 +123,12 @@ __device__ inline int64_t dw_source(const DwArgs &a, int q, int k, bool &extra) 
         extra = true;
         return ((int64_t)q * 5 + c) * nsp;
     }
-    if (a.seg != 0) return ((int64_t)q * DH + k) * nsp;
-    if (k < DH) return (q % Lx) != 0 ? ((int64_t)(q - 1) * DH + k) * nsp : -1;
+    // h and the GLU output: [position][16-sample block][DH][16]; the offset of
+    // sample 0 of column k (sample s adds (s / 16) * 16 DH + s % 16)
+    if (a.seg != 0) return (int64_t)q * DH * nsp + k * 16;
+    if (k < DH) return (q % Lx) != 0 ? (int64_t)(q - 1) * DH * nsp + k * 16 : -1;
     if (q < Lx) return -1;
-    return ((int64_t)site_pos(order_site(q, Lx) - Lx, Lx) * DH + (k - DH)) * nsp;
+    return (int64_t)site_pos(order_site(q, Lx) - Lx, Lx) * DH * nsp + (k - DH) * 16;
 }
 
 // Extra input rows per position: 1, the one-hot of the horizontal
@@ -210,19 +212,31 @@ __global__ __launch_bounds__(512) void dw_mfma(DwArgs a, DwBatch gb) {
         ap[i] = A + (int64_t)(m < a.MD ? m : 0) * nsp + VEC * lq;
     }
     // staging chunks of this thread: row j of the tile, 16-byte part c
-    // (samples VEC*c .. VEC*c + VEC - 1 of the step)
+    // (samples VEC*c .. VEC*c + VEC - 1 of the step); one step is STEP * DH
+    // elements of the blocked h and GLU arrays (16 DH per 16 samples) and STEP
+    // of the extra rows
     const T *bsrc[CPT];
-    int bdst[CPT], boff[CPT];
+    int bdst[CPT], boff[CPT], binc[CPT];
+    const int DHa = a.d.DH;
+    // (chunk order = address order of the blocked arrays: the parts of one
+    // 16-sample block, then the tile's columns, then the blocks of the step)
+    constexpr int PB = 16 / VEC;
 #pragma unroll
     for (int i = 0; i < CPT; i++) {
-        const int ch = tid + 512 * i, j = ch / CPR, c = ch - j * CPR;
+        const int ch = tid + 512 * i, h = ch % PB, jb = ch / PB, j = jb % DW_COLS, c = (jb / DW_COLS) * PB + h;
         bsrc[i] = nullptr;
         bdst[i] = -1;
         boff[i] = VEC * c;
+        binc[i] = 0;
         if (ch < NCH) {
             bool extra;
             const int64_t off = dw_source(a, q, k0 + j, extra);
-            if (off >= 0) bsrc[i] = (extra ? XE : X) + off + VEC * c;
+            if (off >= 0) {
+                // a running pointer: at the chunk's first step, advanced one step per load
+                bsrc[i] = extra ? XE + off + VEC * c + sbeg
+                                : X + off + ((VEC * c) >> 4) * (DHa * 16) + ((VEC * c) & 15) + sbeg * DHa;
+                binc[i] = extra ? STEP : STEP * DHa;
+            }
             bdst[i] = j * LDB + VEC * c;
         }
     }
@@ -246,10 +260,13 @@ __global__ __launch_bounds__(512) void dw_mfma(DwArgs a, DwBatch gb) {
     // part or a k-step lies wholly before or wholly after send; parts past
     // send are zeros)
     uint4 stg[CPT];
+    // (called once per step, in order from sbeg)
     auto gload_b = [&](int64_t s0) {
 #pragma unroll
-        for (int i = 0; i < CPT; i++)
-            stg[i] = (bsrc[i] && s0 + boff[i] < send) ? *(const uint4 *)(bsrc[i] + s0) : make_uint4(0, 0, 0, 0);
+        for (int i = 0; i < CPT; i++) {
+            stg[i] = (bsrc[i] && s0 + boff[i] < send) ? *(const uint4 *)bsrc[i] : make_uint4(0, 0, 0, 0);
+            bsrc[i] += binc[i];
+        }
     };
     auto sstore_b = [&](int buf) {
 #pragma unroll

@@ -25,9 +25,9 @@ struct FwdArgs {
     const int4 *postab;      // [N] facts of each order position (build_postab)
     float *lpc, *phc;        // [ns][N][2] log-conditionals, phase conditionals
     double2 *pre;            // [ns][N] running (log P, phase) after each position, FP64
-    void *act;               // [N][NF*DH][nsp] gate and GLU pre-activations for the backward (store_t)
+    void *act;               // [N][nsp/16][NF*DH][16] gate and GLU pre-activations for the backward (store_t)
     float *lgT;              // [N][4][nsp] logits (l0, l1, z0, z1) for the backward
-    void *hT, *gT;           // with act: transposed h and GLU output [N][DH][nsp] (store_t)
+    void *hT, *gT;           // with act: h and GLU output [N][nsp/16][DH][16] (store_t)
     int64_t nsp;             // sample stride of the transposed arrays
     int64_t ns_cache;        // row count of the cache arrays
     // per-workgroup scratch: column buffer of the 2D chain [grid][Lx][MT][DH]
@@ -57,7 +57,7 @@ struct GradBufs {
     const float *coef_lp, *coef_ph;  // given per-sample coefficients (vector-Jacobian product), or NULL
     double *stats;
     void *dtc, *dtg, *dth;  // transposed deltas (cell, GLU, heads)
-    const void *hT, *gT;    // transposed hidden states and GLU outputs
+    const void *hT, *gT;    // hidden states and GLU outputs, [N][nsp/16][DH][16]
     void *xT;               // transposed extra inputs (bias, one-hots)
     void *dcol;
     float *part;
