@@ -108,7 +108,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_bwd(BwdArgs a0, BatchInfo bi) {
     T *const sBg = (T *)sDyn;
     uint8_t *const sSig = sDyn + (REGW ? (size_t)DH * G_LD * sizeof(T) : 0);
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = w / C::WU, wu = w % C::WU;
     const int l16 = lane & 15, lq = lane >> 4;
     // batched: one problem per group of bi.tiles work-groups

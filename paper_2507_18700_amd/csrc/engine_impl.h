@@ -178,7 +178,7 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
     __shared__ int sTile;
     extern __shared__ uint8_t sSig[];  // [MT][N]
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = w / C::WU, wu = w % C::WU;
     // the arguments of this work-group's problem (a batched row launch: one
     // problem per group of `bi.tiles` work-groups; the batched chain launch
@@ -657,19 +657,22 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
                                 make_float4(hq[0], hq[1], hq[2], hq[3]);
                         if (VEC == 8) put4<P>((T *)a.hcs + ((int64_t)qc * ns_c + s) * DH + u0, hq);
                     }
-                    const int64_t sx = e0 + r;
-                    if (store_act && sx < a.nsp) {
-                        // [position][16-sample block][feature][16]: the 4 units of
-                        // a lane are adjacent 16-sample rows, so the 4 stores of a
-                        // wave fill whole 128-byte lines
-                        T *hb = (T *)a.hT + (int64_t)qc * DH * a.nsp + (sx >> 4) * (DH * 16) + (sx & 15);
-                        T *ab = (T *)a.act + (int64_t)qc * (NA + 2) * DH * a.nsp + (sx >> 4) * ((NA + 2) * DH * 16) +
-                                (sx & 15);
+                    // [position][16-sample block][feature][16]: the 4 units of a
+                    // lane are adjacent 16-sample rows, so the 4 stores of a wave
+                    // fill whole 128-byte lines.  The row block starts at a
+                    // multiple of 16 (e0, the wave's rows and rb * 16 are), so its
+                    // block is uniform across the wave and the lane's sample
+                    // within it is l16; nsp is a multiple of 16
+                    const int64_t row0 = e0 + wr * C::RW + rb * 16;
+                    if (store_act && row0 < a.nsp) {
+                        T *hb = (T *)a.hT + ((int64_t)qc * a.nsp + row0) * DH;
+                        T *ab = (T *)a.act + ((int64_t)qc * a.nsp + row0) * ((NA + 2) * DH);
+                        const uint32_t lo = (uint32_t)(l16 + u0 * 16);
 #pragma unroll
                         for (int i = 0; i < 4; i++) {
-                            hb[(u0 + i) * 16] = cvt<P>(hq[i]);
+                            hb[lo + i * 16] = cvt<P>(hq[i]);
 #pragma unroll
-                            for (int f = 0; f < NA; f++) ab[(f * DH + u0 + i) * 16] = cvt<P>(gv[STORE ? f : 0][i]);
+                            for (int f = 0; f < NA; f++) ab[lo + (f * DH + i) * 16] = cvt<P>(gv[STORE ? f : 0][i]);
                         }
                     }
                 }
@@ -691,19 +694,18 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
                     g[i] = a1[i] * sigmoidf_(a2[i]);
                 }
                 head_part(ub, g, p0, p1, p2, p3);
-                const int64_t sx = e0 + r;
-                if (store_act && sx < a.nsp) {
-                    // (the same 16-sample blocked layout as the cell's arrays)
+                // (the same 16-sample blocked layout as the cell's arrays)
+                const int64_t row0 = e0 + wr * C::RW + rb * 16;
+                if (store_act && row0 < a.nsp) {
                     const bool ok = s >= 0;
-                    const int u0 = unit0(ub);
-                    T *gb = (T *)a.gT + (int64_t)qg * DH * a.nsp + (sx >> 4) * (DH * 16) + (sx & 15);
-                    T *ab = (T *)a.act + (int64_t)qg * (NA + 2) * DH * a.nsp + (sx >> 4) * ((NA + 2) * DH * 16) +
-                            (sx & 15);
+                    T *gb = (T *)a.gT + ((int64_t)qg * a.nsp + row0) * DH;
+                    T *ab = (T *)a.act + ((int64_t)qg * a.nsp + row0) * ((NA + 2) * DH);
+                    const uint32_t lo = (uint32_t)(l16 + unit0(ub) * 16);
 #pragma unroll
                     for (int i = 0; i < 4; i++) {
-                        gb[(u0 + i) * 16] = cvt<P>(ok ? g[i] : 0.f);
-                        ab[(NA * DH + u0 + i) * 16] = cvt<P>(ok ? a1[i] : 0.f);
-                        ab[((NA + 1) * DH + u0 + i) * 16] = cvt<P>(ok ? a2[i] : 0.f);
+                        gb[lo + i * 16] = cvt<P>(ok ? g[i] : 0.f);
+                        ab[lo + (NA * DH + i) * 16] = cvt<P>(ok ? a1[i] : 0.f);
+                        ab[lo + ((NA + 1) * DH + i) * 16] = cvt<P>(ok ? a2[i] : 0.f);
                     }
                 }
             }

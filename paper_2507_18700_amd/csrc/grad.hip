@@ -191,7 +191,7 @@ __global__ __launch_bounds__(512) void dw_mfma(DwArgs a, DwBatch gb) {
     constexpr int CPR = STEP / VEC;                  // 16-byte chunks per staged row
     constexpr int NCH = DW_COLS * CPR, CPT = (NCH + 511) / 512;
     __shared__ __align__(16) T sB[2][DW_COLS * LDB];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, lq = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6), l16 = lane & 15, lq = lane >> 4;
     const int xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
     const int u = xcd + kXcds * (slot / a.tiles);
     if (u >= a.units) return;  // padding slot: the whole work-group leaves before any barrier
