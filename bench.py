@@ -25,6 +25,7 @@ import hashlib
 import json
 import os
 import platform
+import re
 import sys
 import time
 
@@ -45,7 +46,8 @@ PEAK_TRANS_T = 256 * 4 * 8 * 2.4e9 / 1e12
 
 # HBM traffic of the chain kernel, measured with rocprofv3 counters
 # (FETCH_SIZE, WRITE_SIZE, scaled by the same counters on a plain copy of
-# known size); valid only for the engine sources it was measured on.
+# known size); valid only for the engine code it was measured on (the hash
+# covers the code: comments and whitespace do not enter it).
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rnn_engine_chain_tfim2d_10x10_dh128_bf16.json")
 ENGINE_SOURCES = ["engine_impl.h", "engine.hip", "engine_bf16_2d.hip", "common.h", "kernels.h"]
 
@@ -53,8 +55,12 @@ ENGINE_SOURCES = ["engine_impl.h", "engine.hip", "engine_bf16_2d.hip", "common.h
 def engine_source_hash():
     h = hashlib.sha256()
     for f in ENGINE_SOURCES:
-        with open(os.path.join(ROOT, "paper_2507_18700_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2507_18700_amd", "csrc", f)) as fh:
+            src = fh.read()
+        # (the engine sources hold no string literal with a comment marker)
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

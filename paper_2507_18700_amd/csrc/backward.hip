@@ -30,7 +30,7 @@ struct BwdArgs {
     const float *Hd;
     int64_t ns, nsp;
     const uint8_t *cfg;
-    const void *act;        // [N][NF*DH][nsp] gate values and GLU pre-activations (store_t)
+    const void *act;        // [N][nsp/16][NF*DH][16] gate values and GLU pre-activations (store_t)
     const float *lgT;       // [N][4][nsp] logits
     const float *hcache;    // [N][ns][DH] FP32 hidden states (1D: h_{n-1} of the update-gate term)
     const double *eloc, *w, *stats;

@@ -185,9 +185,9 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
     // rebases per tile)
     FwdArgs a = a0;
     // row launches: work-groups go to the XCDs round-robin by id, and a tile
-    // that is not a multiple of 64 rows shares 128-byte lines of the
-    // [unit][sample] activation arrays with its neighbours, so each XCD takes
-    // a contiguous run of tiles (XCD x: G/8 tiles, plus one if x < G % 8)
+    // that is not a multiple of 32 rows shares 128-byte lines of the FP32
+    // [logit][sample] arrays with its neighbours, so each XCD takes a
+    // contiguous run of tiles (XCD x: G/8 tiles, plus one if x < G % 8)
     int row_tile = blockIdx.x;
     if (!CHAIN) {
         const int G = gridDim.x, b = blockIdx.x, x = b % kXcdsE;

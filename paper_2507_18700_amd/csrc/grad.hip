@@ -2,10 +2,12 @@
 // a reverse sweep (backpropagation through the autoregressive chain) that
 // produces the per-(position, sample) deltas of every contraction, and the
 // weight gradients as contractions of those deltas with the layer inputs over
-// all (position, sample) pairs.  Deltas and inputs are stored transposed,
+// all (position, sample) pairs.  Deltas are stored transposed,
 // [position][feature][sample], so the contraction over samples reads MFMA
-// fragments straight from memory; one partial per position (FP32 MFMA
-// accumulation), summed over positions in FP64 in a fixed order.
+// fragments straight from memory; the inputs (h, GLU output) in blocks of 16
+// samples, [position][sample/16][feature][16], staged through LDS.  One
+// partial per position (FP32 MFMA accumulation), summed over positions in FP64
+// in a fixed order.
 //
 // With E held constant, the gradient is that of the surrogate
 //   L = sum_s [a_s log P(sigma_s) + b_s phi(sigma_s)],
@@ -96,7 +98,7 @@ struct DwArgs {
     int64_t ns, nsp;      // samples, padded sample stride
     const void *A;        // transposed deltas [N][MD][nsp]
     int MD, K, Mp, Kp;    // delta rows, hidden input columns, padded output dims
-    const void *hT, *gT;  // transposed hidden states / GLU outputs [N][DH][nsp]
+    const void *hT, *gT;  // hidden states / GLU outputs [N][nsp/16][DH][16]
     const void *xT;       // transposed extra inputs [N][5][nsp]: 1, onehot_hz(2), onehot_vt(2)
     float *part;          // [N*nchunk][Mp][Kp]
     int nchunk;           // sample chunks per position (split of the contraction)
