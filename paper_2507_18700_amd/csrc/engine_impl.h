@@ -747,8 +747,10 @@ __global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, 
                     }
                 };
                 auto cblock = [&](int rb, f32x4_t *acc) __attribute__((always_inline)) {
-                    // scheduling hint: interleave the operand reads with the MFMAs
-                    __builtin_amdgcn_iglp_opt(0);
+                    // scheduling hint: the strategy that interleaves exponentials
+                    // with MFMAs (the gate algebra of the previous row block runs
+                    // beside this block's MFMAs)
+                    __builtin_amdgcn_iglp_opt(3);
                     // start values: bias and one-hot inputs of the row's input class
                     const int cls = sCmb[qc & 1][XT ? wr * C::RW + rb * 16 + l16 : 0];
 #pragma unroll
