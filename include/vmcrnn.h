@@ -147,6 +147,31 @@ vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const u
                     const double *eloc, const double *weights, double *grad, double *stats,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* The gradient of vmc_grad over a sample set too large for one workspace
+ * (Sec. III: the estimator is a weighted sum over independent samples once
+ * Ebar is fixed, so it splits over sample chunks without recomputation):
+ *  vmc_energy_stats: stats [4] double (out) of the whole set, as vmc_grad
+ *    forms them: Re Ebar, Im Ebar, var, non-finite count; eloc [ns][2]
+ *    double, weights [ns] double or NULL (w_s = 1/ns).  Needs no model and
+ *    no workspace; ns >= 1.
+ *  vmc_grad_chunk: the contribution of one chunk of ns samples of that set,
+ *    sum over the chunk of w_s [Re(E_s-Ebar) d logP_s + 2 Im(E_s-Ebar) d phi_s],
+ *    ADDED to grad [vmc_param_count] double (the caller zeroes grad before the
+ *    first chunk).  weights [ns] double is required: the whole set's weights
+ *    of these samples (1/ns_total for an unweighted set); stats [4] double is
+ *    read only (Ebar of the whole set, from vmc_energy_stats).  configs,
+ *    eloc, ws and stream as for vmc_grad with this chunk's ns (workspace of
+ *    vmc_workspace_size(m, NULL, ns) bytes).  Over all chunks the sum equals
+ *    vmc_grad on the whole set up to the FP32 rounding of the per-position
+ *    partial sums (their sample ranges differ) and the FP64 order of the
+ *    chunk additions.  Calls on one stream run in order; grad must not be
+ *    written by another call in between. */
+vmc_status vmc_energy_stats(int64_t ns, const double *eloc, const double *weights, double *stats,
+                            void *stream);
+vmc_status vmc_grad_chunk(const vmc_model *m, const float *params, int64_t ns, const uint8_t *configs,
+                          const double *eloc, const double *weights, const double *stats, double *grad,
+                          void *ws, size_t ws_bytes, void *stream);
+
 /* Vector-Jacobian product of rnn_logpsi (the backward of log psi as a
  * differentiable function of the parameters, Eq. 1 through App. A):
  *   grad[k] = sum_s ( dlogp[s] * d logP(sigma_s)/d theta_k

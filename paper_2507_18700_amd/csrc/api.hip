@@ -31,7 +31,8 @@ int chain_occupancy(const Dims &d);
 int backward_tile_rows(int DH);
 size_t backward_lds(const Dims &d);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
-hipError_t launch_grad(const GradBufs &b, hipStream_t st, const BatchInfo *bi = nullptr);
+hipError_t launch_grad(const GradBufs &b, hipStream_t st, const BatchInfo *bi = nullptr, bool chunk = false);
+hipError_t launch_stats(int64_t ns, const double *eloc, const double *w, double *stats, hipStream_t st);
 void grad_sizes(const Dims &d, int64_t ns, size_t *part_floats);
 int64_t grad_nsp(int64_t ns);
 hipError_t launch_grow(const vmc_model &from, const float *p0, int new_dh, uint64_t seed, double noise,
@@ -422,7 +423,8 @@ static vmc_status eloc_from_cache(const Dims &d, const WsMap &w, void *ws, const
 // configurations.
 static vmc_status grad_from_cache(const Dims &d, const WsMap &w, void *ws, int64_t ns, const uint8_t *configs,
                                   const double *eloc, const double *weights, double *grad, double *stats,
-                                  hipStream_t st, const float *coef_lp = NULL, const float *coef_ph = NULL) {
+                                  hipStream_t st, const float *coef_lp = NULL, const float *coef_ph = NULL,
+                                  bool chunk = false) {
     GradBufs b;
     b.d = d;
     b.BcT = at<void>(ws, w.BcT);
@@ -448,7 +450,7 @@ static vmc_status grad_from_cache(const Dims &d, const WsMap &w, void *ws, int64
     b.xT = at<void>(ws, w.xT);
     b.part = at<float>(ws, w.part);
     b.grad = grad;
-    return hip_status(launch_grad(b, st));
+    return hip_status(launch_grad(b, st, nullptr, chunk));
 }
 
 vmc_status local_energy(const vmc_model *m, const float *params, const vmc_ham *H, int64_t ns,
@@ -498,6 +500,38 @@ vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const u
     e = launch_forward(a, MODE_LOGPSI, 1, 0, 1, w.fwd_grid, st);
     if (e != hipSuccess) return VMC_EDEVICE;
     return grad_from_cache(d, w, ws, ns, configs, eloc, weights, grad, stats, st);
+}
+
+vmc_status vmc_energy_stats(int64_t ns, const double *eloc, const double *weights, double *stats, void *stream) {
+    if (ns <= 0) return VMC_EINVAL;
+    if (!eloc || !stats) return VMC_EINVAL;
+    return hip_status(launch_stats(ns, eloc, weights, stats, (hipStream_t)stream));
+}
+
+vmc_status vmc_grad_chunk(const vmc_model *m, const float *params, int64_t ns, const uint8_t *configs,
+                          const double *eloc, const double *weights, const double *stats, double *grad, void *ws,
+                          size_t ws_bytes, void *stream) {
+    vmc_status s = check_common(m, params, ns, ws, ws_bytes, NULL, NULL);
+    if (s != VMC_OK) return s;
+    if (!configs || !eloc || !weights || !stats || !grad) return VMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Dims d = make_dims(m);
+    WsMap w = ws_map(d, NULL, ns);
+    hipError_t e = stage(d, params, ws, w, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    FwdArgs a = base_args(d, ws, w, ns);
+    a.cfg_in = configs;
+    a.hcache = at<float>(ws, w.hcache);
+    a.act = at<void>(ws, w.act);
+    a.lgT = at<float>(ws, w.lgT);
+    a.hT = at<void>(ws, w.hT);
+    a.gT = at<void>(ws, w.gT);
+    a.nsp = w.nsp;
+    e = launch_forward(a, MODE_LOGPSI, 1, 0, 1, w.fwd_grid, st);
+    if (e != hipSuccess) return VMC_EDEVICE;
+    // (the statistics are read, never written: the cast only fits the buffer type)
+    return grad_from_cache(d, w, ws, ns, configs, eloc, weights, grad, const_cast<double *>(stats), st, NULL, NULL,
+                           true);
 }
 
 vmc_status rnn_logpsi_grad(const vmc_model *m, const float *params, int64_t nc, const uint8_t *configs,

@@ -388,7 +388,7 @@ __device__ inline int64_t dw_param(const Dims &d, int seg, int m, int k) {
 // row: 8 groups of 32 threads take every 8th partial (4 loads in flight per
 // thread), then the 8 group sums are added in a fixed order.
 __global__ __launch_bounds__(256) void dw_reduce(Dims d, int seg, const float *part, int Q, int Mp, int Kp, int K,
-                                                 int MD, double *grad, DwBatch gb) {
+                                                 int MD, double *grad, DwBatch gb, int accumulate) {
     __shared__ double sg[8][32];
     if (gb.n > 0) {  // batch: problem blockIdx.y
         const int kk = blockIdx.y;
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(256) void dw_reduce(Dims d, int seg, const float *p
         double t = 0.0;
         for (int i = 0; i < 8; i++) t += sg[i][threadIdx.x];
         const int64_t idx = dw_param(d, seg, m, k);
-        if (idx >= 0) grad[idx] = t;
+        if (idx >= 0) grad[idx] = accumulate ? grad[idx] + t : t;
     }
 }
 
@@ -514,14 +514,22 @@ static void launch_dw_p(const DwArgs &a, const SegDims &sd, const DwBatch &gb, i
 
 hipError_t launch_backward(const GradBufs &b, int64_t nsp, hipStream_t st, const BatchInfo *bi);
 
+// Ebar, var and the non-finite count of ns local energies into stats[4].
+hipError_t launch_stats(int64_t ns, const double *eloc, const double *w, double *stats, hipStream_t st) {
+    hipLaunchKernelGGL(stats_kernel, dim3(1, 1), dim3(1024), 0, st, ns, eloc, w, stats);
+    return hipGetLastError();
+}
+
 // bi: NULL, or the batch of vmc_step_batched; b then describes problem 0 with
 // the longest chain's sizes (grad and stats of problem k at k * pitch_p and
 // k * 4, local energies at k * 2 ns).
-hipError_t launch_grad(const GradBufs &b, hipStream_t st, const BatchInfo *bi) {
+// chunk: the samples are one chunk of a larger set: b.stats holds that set's
+// statistics (not computed here) and the chunk's gradient is added to b.grad.
+hipError_t launch_grad(const GradBufs &b, hipStream_t st, const BatchInfo *bi, bool chunk) {
     const Dims &d = b.d;
     const int nb = bi ? bi->n : 0;
-    if (nb > 0 && (b.coef_lp || b.weights)) return hipErrorInvalidValue;
-    if (!b.coef_lp)
+    if (nb > 0 && (b.coef_lp || b.weights || chunk)) return hipErrorInvalidValue;
+    if (!b.coef_lp && !chunk)
         hipLaunchKernelGGL(stats_kernel, dim3(1, nb > 0 ? nb : 1), dim3(1024), 0, st, b.ns, b.eloc, b.weights,
                            b.stats);
     hipError_t e = launch_backward(b, grad_nsp(b.ns), st, bi);
@@ -557,8 +565,9 @@ hipError_t launch_grad(const GradBufs &b, hipStream_t st, const BatchInfo *bi) {
     }
     const int64_t P = param_layout(d.dims, d.dh, d.glu, d.cplx).total;
     const int64_t Pall = nb > 0 ? (int64_t)(nb - 1) * bi->pitch_p + P : P;
-    hipLaunchKernelGGL(fill_f64, dim3((int)((Pall + 255) / 256 < 4096 ? (Pall + 255) / 256 : 4096)), dim3(256), 0, st,
-                       b.grad, Pall, 0.0);
+    if (!chunk)
+        hipLaunchKernelGGL(fill_f64, dim3((int)((Pall + 255) / 256 < 4096 ? (Pall + 255) / 256 : 4096)), dim3(256), 0,
+                           st, b.grad, Pall, 0.0);
     for (int seg = 0; seg < 3; seg++) {
         if (seg == 1 && !d.glu) continue;
         SegDims sd = seg_dims(d, seg);
@@ -590,7 +599,7 @@ hipError_t launch_grad(const GradBufs &b, hipStream_t st, const BatchInfo *bi) {
         else launch_dw_p<F32>(a, sd, gbs[seg], units_max, st);
         const int rg = sd.MD * ((sd.K + 5 + 31) / 32);
         hipLaunchKernelGGL(dw_reduce, dim3(rg, nb > 0 ? nb : 1), dim3(256), 0, st, d, seg, b.part, d.N * a.nchunk,
-                           sd.Mp, sd.Kp, sd.K, sd.MD, b.grad, gbs[seg]);
+                           sd.Mp, sd.Kp, sd.K, sd.MD, b.grad, gbs[seg], chunk ? 1 : 0);
     }
     return hipGetLastError();
 }

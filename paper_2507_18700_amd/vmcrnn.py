@@ -19,7 +19,7 @@ VMC_TFIM, VMC_HEISENBERG, VMC_LRTFIM, VMC_CLUSTER = 0, 1, 2, 3
 VMC_EINVAL, VMC_EUNSUPPORTED, VMC_ENOSPACE, VMC_EDEVICE, VMC_ENONFINITE = -1, -2, -3, -4, -5
 
 EXPORTS = ("vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "rnn_logpsi_grad", "local_energy",
-           "vmc_grad", "vmc_step", "vmc_step_batched", "vmc_batched_workspace_size", "vmc_step_noalloc",
+           "vmc_grad", "vmc_energy_stats", "vmc_grad_chunk", "vmc_step", "vmc_step_batched", "vmc_batched_workspace_size", "vmc_step_noalloc",
            "vmc_noalloc_scratch_bytes", "vmc_adam", "vmc_check_finite",
            "grow_hidden", "vmc_row_tile_options",
            "vmc_set_tuning", "vmc_get_tuning", "vmc_autotune_step", "vmc_chain_timing", "vmc_chain_time",
@@ -98,6 +98,10 @@ def lib():
         L.local_energy.argtypes = [P(Model), vp, P(Ham), i64, vp, vp, vp, sz, vp]
         L.vmc_grad.restype = ctypes.c_int
         L.vmc_grad.argtypes = [P(Model), vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.vmc_energy_stats.restype = ctypes.c_int
+        L.vmc_energy_stats.argtypes = [i64, vp, vp, vp, vp]
+        L.vmc_grad_chunk.restype = ctypes.c_int
+        L.vmc_grad_chunk.argtypes = [P(Model), vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
         L.vmc_step.restype = ctypes.c_int
         L.vmc_step.argtypes = [P(Model), vp, P(Ham), i64, u64, u64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.vmc_step_batched.restype = ctypes.c_int
@@ -326,6 +330,51 @@ def vmc_grad(m, params, configs, eloc, weights=None, ws=None, out=None):
     buf, nb = _ws(ws, m, None, ns)
     _check(lib().vmc_grad(ctypes.byref(m), _ptr(params), ns, _ptr(configs), _ptr(eloc), _ptr(weights), _ptr(g),
                           _ptr(st), _ptr(buf), nb, _stream()))
+    return g, st
+
+
+def energy_stats(eloc, weights=None, out=None):
+    """Re Ebar, Im Ebar, var and the non-finite count of a set of local
+    energies, as vmc_grad forms them; returns stats float64 [4]."""
+    if not (isinstance(eloc, torch.Tensor) and eloc.dim() == 2 and eloc.shape[1] == 2):
+        raise ValueError("eloc must be a [ns, 2] tensor")
+    ns = eloc.shape[0]
+    if ns < 1:
+        raise ValueError("eloc holds no sample")
+    _dev(eloc, torch.float64, "eloc", (ns, 2))
+    if weights is not None:
+        _dev(weights, torch.float64, "weights", (ns,))
+    st = out if out is not None else torch.empty(4, dtype=torch.float64, device=eloc.device)
+    _dev(st, torch.float64, "stats", (4,))
+    _check(lib().vmc_energy_stats(ns, _ptr(eloc), _ptr(weights), _ptr(st), _stream()))
+    return st
+
+
+def vmc_grad_chunked(m, params, configs, eloc, weights, chunk, out=None):
+    """vmc_grad of a sample set in chunks of at most `chunk` samples, each in
+    a workspace sized for one chunk: the set's statistics first, then every
+    chunk's contribution added to the gradient by the library.  weights
+    float64 [ns] (1/ns for an unweighted set) is required.  Returns
+    (grad float64 [P], stats float64 [4])."""
+    _params(m, params)
+    ns = _configs(m, configs)
+    _dev(eloc, torch.float64, "eloc", (ns, 2))
+    _dev(weights, torch.float64, "weights", (ns,))
+    if not isinstance(chunk, int) or chunk < 1:
+        raise ValueError("chunk must be a positive int")
+    if out is None:
+        out = (torch.empty(param_count(m), dtype=torch.float64, device=params.device),
+               torch.empty(4, dtype=torch.float64, device=params.device))
+    g, st = out
+    _dev(g, torch.float64, "grad", (param_count(m),))
+    energy_stats(eloc, weights, out=st)
+    g.zero_()
+    buf, nb = _ws(None, m, None, min(chunk, ns))
+    for s0 in range(0, ns, chunk):
+        n = min(chunk, ns - s0)
+        _check(lib().vmc_grad_chunk(ctypes.byref(m), _ptr(params), n, _ptr(configs[s0:s0 + n]),
+                                    _ptr(eloc[s0:s0 + n]), _ptr(weights[s0:s0 + n]), _ptr(st), _ptr(g),
+                                    _ptr(buf), nb, _stream()))
     return g, st
 
 

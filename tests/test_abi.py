@@ -32,7 +32,7 @@ def lib():
 def test_exports_every_declared_symbol(lib):
     names = declared()
     assert set(names) == {"vmc_param_count", "vmc_workspace_size", "rnn_sample", "rnn_logpsi", "rnn_logpsi_grad",
-                          "local_energy", "vmc_grad", "vmc_step", "vmc_step_batched", "vmc_batched_workspace_size",
+                          "local_energy", "vmc_grad", "vmc_energy_stats", "vmc_grad_chunk", "vmc_step", "vmc_step_batched", "vmc_batched_workspace_size",
                           "vmc_step_noalloc", "vmc_noalloc_scratch_bytes",
                           "vmc_adam", "vmc_check_finite", "grow_hidden",
                           "vmc_row_tile_options", "vmc_set_tuning", "vmc_get_tuning", "vmc_autotune_step",
@@ -89,6 +89,13 @@ def test_argument_errors_before_launch(lib):
     assert L.rnn_logpsi(ctypes.byref(m), None, 100, fake, fake, None, ws, need, None) == -1
     assert L.vmc_grad(ctypes.byref(m), fake, 100, fake, None, None, fake, None, ws, need, None) == -1
     assert L.rnn_logpsi_grad(ctypes.byref(m), fake, 100, fake, None, None, fake, ws, need, None) == -1
+    # chunked gradient: the whole set's weights and statistics are required; no samples
+    assert L.vmc_grad_chunk(ctypes.byref(m), fake, 100, fake, fake, None, fake, fake, ws, need, None) == -1
+    assert L.vmc_grad_chunk(ctypes.byref(m), fake, 100, fake, fake, fake, None, fake, ws, need, None) == -1
+    assert L.vmc_grad_chunk(ctypes.byref(m), fake, 100, fake, fake, fake, fake, fake, ws, need - 1, None) == -3
+    assert L.vmc_energy_stats(0, fake, None, fake, None) == -1
+    assert L.vmc_energy_stats(100, None, None, fake, None) == -1
+    assert L.vmc_energy_stats(100, fake, None, None, None) == -1
     assert L.rnn_logpsi_grad(ctypes.byref(m), fake, 100, fake, fake, None, fake, ws, need - 1, None) == -3
     assert L.local_energy(ctypes.byref(m), fake, None, 100, fake, fake, ws, need, None) == -1
     badH = lib.Ham(5, 0, 1.0, 1.0)

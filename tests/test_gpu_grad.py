@@ -185,3 +185,63 @@ def test_logpsi_autograd(case, bf16):
     tol = 1e-2 if bf16 else 1e-5
     err = rel_l2(g.double().cpu().numpy(), ref)
     assert err < tol, "relative l2 error %.3g" % err
+
+
+@pytest.mark.parametrize("case", [(2, 4, 3, 64, False, True), (1, 12, 1, 32, True, True)],
+                         ids=["2D_4x3_dh64_glu", "1D_12_dh32_cplx_glu"])
+@pytest.mark.parametrize("bf16", [False, True], ids=["fp32", "bf16"])
+@pytest.mark.parametrize("weighted", [False, True], ids=["uniform", "weighted"])
+def test_grad_in_sample_chunks(case, bf16, weighted):
+    """The gradient of a sample set in chunks (ragged: 97 = 40 + 40 + 17), each
+    in a workspace for one chunk, against vmc_grad on the whole set: the same
+    statistics bit for bit, the gradient up to the FP32 rounding of the
+    per-position partial sums over different sample ranges; and against the
+    FP64 oracle at the usual bar."""
+    torch = torch_gpu()
+    from oracle import oracle as O
+    from paper_2507_18700_amd import vmcrnn as V
+    dims, Lx, Ly, dh, cplx, glu = case
+    spec, gm, _ = lib_and_oracle(dims, Lx, Ly, dh, cplx, glu, bf16)
+    _, _, om = lib_and_oracle(dims, Lx, Ly, dh, cplx, glu, False)
+    p = synth.xavier_params(spec, 41, bias_scale=0.2)
+    ns = 97
+    cfg = synth.configs(ns, spec.N, 42)
+    e = synth.eloc_values(ns, 43, complex_=cplx, scale=2.0)
+    e[:, 0] -= 5.0
+    if weighted:
+        w = np.random.default_rng(44).random(ns)
+        w /= w.sum()
+    else:
+        w = np.full(ns, 1.0 / ns)
+    P, C, E, W = (torch.from_numpy(x).cuda() for x in (p, cfg, e, w))
+    g0, s0 = V.vmc_grad(gm, P, C, E, weights=W if weighted else None)
+    g0, s0 = g0.clone(), s0.clone()
+    g1, s1 = V.vmc_grad_chunked(gm, P, C, E, W, chunk=40)
+    g1, s1 = g1.clone(), s1.clone()
+    g2, _ = V.vmc_grad_chunked(gm, P, C, E, W, chunk=40)  # repeatable
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+    assert np.array_equal(s1.cpu().numpy(), s0.cpu().numpy())
+    g0n, g1n = g0.cpu().numpy(), g1.cpu().numpy()
+    assert rel_l2(g1n, g0n) < 1e-5, rel_l2(g1n, g0n)
+    rg, _ = O.grad(om, p.astype(np.float64), cfg, e, w if weighted else None)
+    assert rel_l2(g1n, rg) < (1e-2 if bf16 else 1e-5)
+
+
+def test_energy_stats():
+    """The statistics entry on its own: the oracle's Ebar and variance, FP64;
+    a non-finite local energy is counted."""
+    torch = torch_gpu()
+    from oracle import oracle as O
+    from paper_2507_18700_amd import vmcrnn as V
+    ns = 5000
+    e = synth.eloc_values(ns, 51, complex_=True, scale=3.0)
+    w = np.random.default_rng(52).random(ns)
+    w /= w.sum()
+    for wt in (None, w):
+        st = V.energy_stats(torch.from_numpy(e).cuda(), None if wt is None else torch.from_numpy(wt).cuda())
+        ref = O.stats(e, wt)
+        st = st.cpu().numpy()
+        assert np.allclose(st[:3], ref[:3], rtol=1e-13, atol=1e-13) and st[3] == 0
+    e[17, 1] = np.nan
+    assert V.energy_stats(torch.from_numpy(e).cuda()).cpu().numpy()[3] == 1
