@@ -141,3 +141,20 @@ def _heisenberg_connections(sigma, Lx, Ly):
             conn.append(t)
             coef.append(-0.5)
     return np.array(conn, dtype=np.uint8), np.array(coef), diag
+
+
+@pytest.mark.parametrize("case", [FULL[2], FULL[3]], ids=lambda c: c[0])
+def test_full_size_gradient_in_chunks(case):
+    """The bench's step at full size, its gradient again in sample chunks of a
+    quarter of the set (each in a workspace for one chunk): the statistics bit
+    for bit, the gradient within the FP32 rounding of the per-position partial
+    sums over different sample ranges."""
+    torch, O, V, spec, gm, om, om_emul, p, H, oh, ns, bf16 = _setup(case)
+    cfg, lp, ph, e, g, st = V.vmc_step(gm, p, H, ns, seed=7, counter=3)
+    g, st = g.clone(), st.clone()
+    w = torch.full((ns,), 1.0 / ns, dtype=torch.float64, device=p.device)
+    g1, s1 = V.vmc_grad_chunked(gm, p, cfg, e, w, chunk=(ns + 3) // 4)
+    torch.cuda.synchronize()
+    assert torch.equal(s1, st)
+    err = rel_l2(g1.cpu().numpy(), g.cpu().numpy())
+    assert err < 1e-5, err
