@@ -143,9 +143,14 @@ struct PosInfo {
 // CPX: the complex (phase) head fixed at compile time (0 or 1) or read at run
 // time (-1).  The chain launch is instantiated for both values: without the
 // run-time branches its epilogue basic blocks are larger and better scheduled.
+// (waves per SIMD the compiler must allow: what the work-group size implies,
+// except for the 1D d_h = 64 chain launch, which is latency-bound and runs
+// faster with three 4-wave work-groups per compute unit at 168 registers, a
+// few spilled, than with two at 184)
 template <class P, int DIMS, int DH, int NW, int REGW, int STORE, int TF, int TC, int CPX = -1, int BATCH = 0>
-__global__ __launch_bounds__(NW * 64) void rnn_engine(FwdArgs a0, BatchInfo bi, int mode, int store_h_,
-                                                      int store_lpc_, int store_act_) {
+__global__ __launch_bounds__(NW * 64)
+__attribute__((amdgpu_waves_per_eu((DIMS == 1 && DH == 64 && TC == 1) ? 3 : (NW * 64 + 255) / 256)))
+void rnn_engine(FwdArgs a0, BatchInfo bi, int mode, int store_h_, int store_lpc_, int store_act_) {
     // cache writes exist only in the STORE variant (the chain kernel has none)
     const int store_h = STORE && store_h_, store_lpc = STORE && store_lpc_, store_act = STORE && store_act_;
     // the launch mode is fixed by the instantiation: the chain tile class runs
