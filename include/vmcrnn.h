@@ -165,7 +165,10 @@ vmc_status vmc_grad(const vmc_model *m, const float *params, int64_t ns, const u
  *    vmc_grad on the whole set up to the FP32 rounding of the per-position
  *    partial sums (their sample ranges differ) and the FP64 order of the
  *    chunk additions.  Calls on one stream run in order; grad must not be
- *    written by another call in between. */
+ *    written by another call in between.
+ * Errors (before any launch): VMC_EINVAL for ns < 1 or a NULL eloc, stats,
+ * weights (vmc_grad_chunk), configs or grad; the model, parameter and
+ * workspace checks of vmc_grad (VMC_EUNSUPPORTED, VMC_ENOSPACE). */
 vmc_status vmc_energy_stats(int64_t ns, const double *eloc, const double *weights, double *stats,
                             void *stream);
 vmc_status vmc_grad_chunk(const vmc_model *m, const float *params, int64_t ns, const uint8_t *configs,
